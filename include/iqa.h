@@ -1,0 +1,179 @@
+/*
+ * iqa.h -- C ABI of the MI355X (gfx950) tile-wise LISI / augLISI library.
+ *
+ * The library computes, for two N x N single-precision images x and y, the
+ * image-quality-assessment (IQA) matrices of Li, Adamek & Armour, "GPU
+ * Accelerated Image Quality Assessment-Based Software for Transient
+ * Detection":
+ *
+ *   - pre-processing (Sec. 2): negative pixels count as zero.  NaN pixels are
+ *     read as blank sky and count as zero too; -0 counts as +0.
+ *   - the images are cut into (N/N_T)^2 tiles of N_T x N_T pixels (Sec. 2);
+ *     tile t = ty*(N/N_T) + tx covers rows ty*N_T .. ty*N_T+N_T-1 and
+ *     columns tx*N_T .. tx*N_T+N_T-1 of the row-major image.
+ *   - per tile, with x', y' the clamped pixels (Eq. 1, Eq. 2, Sec. 1):
+ *       A  = sum (x'+y') / (|x'-y'| + C1)        P  = sum (x'+y') * |x'-y'|
+ *       Sx = sum x'                              Sy = sum y'
+ *       lisi_t    = D * A / (max(Sx, Sy) + C2)                       Eq. (1)
+ *       auglisi_t = 1 - P / (Sx + Sy + C)                            Eq. (2)
+ *
+ * Every entry point reads both images exactly once from device memory.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * Memory.  x, y and every output are DEVICE pointers owned by the caller, on
+ *   the device that is current on the calling host thread.  Images are dense,
+ *   row-major (column index fastest), N*N floats each.  Inputs are read-only.
+ *   Inputs and outputs must not overlap.  IQA matrices are row-major
+ *   (N/N_T) x (N/N_T) floats; `sums` holds 4 floats per tile in tile order:
+ *   A, P, Sx, Sy.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *   default stream).  Work is enqueued on it and the call returns without
+ *   waiting; results are valid once the caller synchronises that stream.
+ *   Calls on the same stream are ordered; calls on different streams may run
+ *   concurrently.
+ * Scratch.  Shapes with few, large tiles split a tile's rows over several
+ *   workgroups whose partial sums a second, small kernel combines on the same
+ *   stream; those launches use a small library-owned device workspace per
+ *   (device, stream) (16 bytes per tile and split part), allocated on first
+ *   use and reused afterwards.  The first call for a given (device, stream,
+ *   shape) must therefore not happen while the stream is being captured into
+ *   a graph: call iqa_prepare() (or the entry point itself) once before.
+ * Errors.  Every entry point validates its arguments before touching the GPU
+ *   and returns a status; nothing is launched when the status is not IQA_OK.
+ *   Launch failures are reported as IQA_ERR_HIP, with the HIP error code
+ *   available from iqa_last_hip_error() on the same host thread.  No entry
+ *   point aborts or throws.
+ * Preconditions that are not checked: pixels are finite or NaN (not +-Inf) and
+ *   of magnitude at most 2^50, so that the per-tile sums stay finite in FP32.
+ * Precision.  Per-pixel terms are FP32; tile sums are Kahan-compensated FP32;
+ *   augLISI is finalised in double-float arithmetic.  Results are bitwise
+ *   reproducible run to run for a given launch configuration (no floating-point
+ *   atomics) and bitwise symmetric under swapping x and y.
+ */
+#ifndef IQA_H
+#define IQA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum iqa_status {
+    IQA_OK = 0,
+    IQA_ERR_NULL = 1,    /* a required pointer is NULL, or no output requested */
+    IQA_ERR_SHAPE = 2,   /* N or N_T not positive, N % N_T != 0, or N too large */
+    IQA_ERR_ALIGN = 3,   /* a float pointer is not 4-byte aligned (sums: 16-byte) */
+    IQA_ERR_PARAM = 4,   /* D, C1, C2 or C is not a positive, finite, normal float */
+    IQA_ERR_HIP = 5,     /* a HIP runtime call or kernel launch failed */
+    IQA_ERR_CONFIG = 6,  /* a launch configuration is invalid for the shape, or the
+                            shape needs more than 2^31-1 workgroups */
+    IQA_ERR_CAPTURE = 7  /* workspace would have to grow while the stream is captured */
+} iqa_status;
+
+/* Largest supported image side: 2^17 pixels (64 GiB per FP32 image). */
+#define IQA_MAX_N ((int64_t)1 << 17)
+
+/* ------------------------------------------------------------------------ */
+/* Single image pair                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Fused LISI + augLISI over every tile (Eq. 1 and Eq. 2 per tile, after the
+ * clamp of Sec. 2), reading x and y once.
+ *   x, y      device, N*N floats each, row-major.
+ *   N, NT     image side and tile side; N % NT == 0, 1 <= N <= IQA_MAX_N.
+ *   D, C1, C2 LISI constants (Eq. 1); C the augLISI constant (Eq. 2); each a
+ *             positive, finite, normal float (the paper asks C1, C2, C << 1;
+ *             D = C1/2 makes LISI(x, x) = S/(S + C2) ~ 1).
+ *   lisi      device, (N/NT)^2 floats, or NULL to skip.
+ *   auglisi   device, (N/NT)^2 floats, or NULL to skip.
+ *   sums      device, 4*(N/NT)^2 floats (A, P, Sx, Sy per tile), 16-byte
+ *             aligned, or NULL.
+ *   stream    hipStream_t.
+ * At least one of lisi, auglisi, sums must be non-NULL. */
+iqa_status iqa_tiles(const float *x, const float *y, int64_t N, int64_t NT,
+                     float D, float C1, float C2, float C,
+                     float *lisi, float *auglisi, float *sums, void *stream);
+
+/* LISI only (Eq. 1 per tile).  Same conventions as iqa_tiles; the values are
+ * bitwise identical to iqa_tiles' lisi output. */
+iqa_status lisi_tiles(const float *x, const float *y, int64_t N, int64_t NT,
+                      float D, float C1, float C2, float *lisi, void *stream);
+
+/* augLISI only (Eq. 2 per tile).  Same conventions as iqa_tiles; the values
+ * are bitwise identical to iqa_tiles' auglisi output. */
+iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT,
+                         float C, float *auglisi, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Launch configuration (for the autotuner and for reproducible benchmarks)  */
+/* ------------------------------------------------------------------------ */
+
+/* How one launch maps the tiles onto the GPU.  A wave of 64 lanes is cut into
+ * groups of seg*rp lanes, one group per tile: `seg` lanes stream along a tile
+ * row in `vec`-float loads and `rp` such segments take interleaved rows, so a
+ * wave covers ht = 64/(seg*rp) adjacent tiles and reduces them without LDS.
+ * A workgroup of `waves` waves splits those tiles' rows into contiguous
+ * slices (combined in LDS); `ksplit` workgroups split them further (combined
+ * by a second kernel on the same stream).  `unroll` rows per lane are loaded
+ * while the previous `unroll` are reduced. */
+typedef struct iqa_launch_cfg {
+    int32_t vec;     /* floats per lane load: 4, 2 or 1; NT % vec == 0 */
+    int32_t waves;   /* waves per workgroup: 1, 2, 4 or 8 (vec 4); 1 or 4 (vec 1, 2) */
+    int32_t unroll;  /* rows per load batch: 4 or 8 (vec 4); 4 (vec 1, 2) */
+    int32_t seg;     /* lanes per tile row segment: power of two, 1..64 */
+    int32_t rp;      /* row phases per tile in a wave: power of two, seg*rp <= 64 */
+    int32_t ksplit;  /* workgroups per tile group: >= 1; NT % (waves*ksplit) == 0 */
+} iqa_launch_cfg;
+
+/* The configuration iqa_tiles uses for (N, NT) and the given image pointers
+ * (the pointers only matter through their alignment).  Returns IQA_ERR_SHAPE
+ * for shapes iqa_tiles would reject. */
+iqa_status iqa_default_cfg(int64_t N, int64_t NT, const float *x, const float *y,
+                           iqa_launch_cfg *cfg);
+
+/* Check an explicit configuration against a shape: IQA_OK or IQA_ERR_CONFIG. */
+iqa_status iqa_check_cfg(int64_t N, int64_t NT, const iqa_launch_cfg *cfg);
+
+/* iqa_tiles with an explicit launch configuration (NULL = default).  Results
+ * for a given configuration are bitwise reproducible; different
+ * configurations sum in different orders and agree to rounding. */
+iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT,
+                         float D, float C1, float C2, float C,
+                         float *lisi, float *auglisi, float *sums,
+                         const iqa_launch_cfg *cfg, void *stream);
+
+/* Allocate, ahead of time, the workspace that (N, NT) with `cfg` (NULL =
+ * default) needs on `stream`, so that later calls allocate nothing (e.g.
+ * under graph capture).  IQA_OK when nothing or everything was allocated. */
+iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Streaming-read reference kernel, for measurement only: `blocks`
+ * workgroups each sum a contiguous share of the n floats at `buf` (device,
+ * 16-byte aligned, n % 4 == 0) and write one float each to `out` (device,
+ * `blocks` floats).  Its bandwidth is the attainable HBM read rate that the
+ * tile kernels are compared with; the sums themselves carry no meaning. */
+iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blocks,
+                            void *stream);
+
+/* Static, human-readable name of a status code. */
+const char *iqa_status_str(int status);
+
+/* The HIP error code behind the last IQA_ERR_HIP on this host thread (0 if
+ * none). */
+int iqa_last_hip_error(void);
+
+/* Library ABI version: major*10000 + minor*100 + patch. */
+int iqa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IQA_H */

@@ -1,0 +1,95 @@
+"""ctypes loader for the HIP library ``libiqa_hip.so`` (C ABI of include/iqa.h).
+
+The library is required: if it is missing or fails to load, every entry point
+raises.  There is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libiqa_hip.so")
+
+IQA_OK = 0
+STATUS_NAMES = {
+    0: "IQA_OK", 1: "IQA_ERR_NULL", 2: "IQA_ERR_SHAPE", 3: "IQA_ERR_ALIGN",
+    4: "IQA_ERR_PARAM", 5: "IQA_ERR_HIP", 6: "IQA_ERR_CONFIG", 7: "IQA_ERR_CAPTURE",
+}
+
+
+class LaunchCfg(ctypes.Structure):
+    """Mirror of ``iqa_launch_cfg``."""
+
+    _fields_ = [("vec", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("seg", ctypes.c_int32),
+                ("rp", ctypes.c_int32), ("ksplit", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "LaunchCfg":
+        return cls(**{k: int(d[k]) for k, _ in cls._fields_})
+
+
+class IqaError(RuntimeError):
+    def __init__(self, status: int, where: str, hip_error: int = 0):
+        self.status = status
+        self.hip_error = hip_error
+        msg = _status_str(status)
+        if hip_error:
+            msg += f" (hip error {hip_error})"
+        super().__init__(f"{where}: {msg}")
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def _status_str(status: int) -> str:
+    try:
+        return load().iqa_status_str(status).decode()
+    except Exception:  # noqa: BLE001 - best effort while reporting an error
+        return STATUS_NAMES.get(status, f"status {status}")
+
+
+def load() -> ctypes.CDLL:
+    """Load ``libiqa_hip.so`` and declare every entry point's signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"HIP library {LIB_PATH} is not built; run `python -m paper_2501_10653_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    f = ctypes.c_float
+    cfgp = ctypes.POINTER(LaunchCfg)
+    sigs = {
+        "iqa_tiles": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, vp], ctypes.c_int),
+        "lisi_tiles": ([vp, vp, i64, i64, f, f, f, vp, vp], ctypes.c_int),
+        "auglisi_tiles": ([vp, vp, i64, i64, f, vp, vp], ctypes.c_int),
+        "iqa_default_cfg": ([i64, i64, vp, vp, cfgp], ctypes.c_int),
+        "iqa_check_cfg": ([i64, i64, cfgp], ctypes.c_int),
+        "iqa_tiles_cfg": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp], ctypes.c_int),
+        "iqa_prepare": ([i64, i64, cfgp, vp], ctypes.c_int),
+        "iqa_read_ceiling": ([vp, i64, vp, i64, vp], ctypes.c_int),
+        "iqa_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "iqa_last_hip_error": ([], ctypes.c_int),
+        "iqa_version": ([], ctypes.c_int),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != IQA_OK:
+        hip = load().iqa_last_hip_error() if status == 5 else 0
+        raise IqaError(status, where, hip)

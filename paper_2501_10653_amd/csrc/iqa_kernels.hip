@@ -1,0 +1,848 @@
+// Tile-wise LISI / augLISI on gfx950: one fused streaming pass over both images.
+//
+// What is computed (Li, Adamek & Armour, Sec. 1-3): after the Sec. 2 clamp of
+// negative pixels to zero, every N_T x N_T tile gets
+//   A = sum (x'+y')/(|x'-y'|+C1),  P = sum (x'+y')|x'-y'|,  Sx = sum x',  Sy = sum y'
+//   lisi = D*A/(max(Sx,Sy)+C2)  (Eq. 1),   auglisi = 1 - P/(Sx+Sy+C)  (Eq. 2).
+//
+// How (MI355X design, not the paper's block-per-tile shared-memory scheme):
+//   * The work is HBM-bound: 8 bytes per pixel pair against ~18 VALU slots, so
+//     the kernel's job is to keep enough 128-bit loads in flight and to spend
+//     as few instructions as possible outside the per-pixel loop.
+//   * A wave of 64 lanes is cut into groups of seg*rp lanes, one group per
+//     tile: `seg` lanes stream along a tile row (seg*vec floats wide) and `rp`
+//     such segments take interleaved rows.  So a wave covers 64/(seg*rp)
+//     adjacent tiles, and a whole tile slice reduces inside one wave with DPP
+//     lane permutations, with no LDS and no barrier.  Several waves of a
+//     workgroup may share a tile's rows (combined once in LDS), and for shapes
+//     with few large tiles several workgroups share them (combined by a second,
+//     tiny kernel that runs after the first on the same stream).
+//   * Each lane folds `vec` adjacent pixels with plain FP32 (FMA chains) and
+//     adds the block into Kahan-compensated (hi, lo) accumulators: the long
+//     per-lane sums are compensated.  Across lanes the partial sums are folded
+//     to one float and added plainly: every partial is non-negative, so a tree
+//     of depth d adds at most d units of roundoff, relative.
+//   * Loads are double-buffered: the next `unroll` rows are in flight while the
+//     current ones are reduced.
+//   * Every reduction has a fixed order and there are no floating-point
+//     atomics, so results are bitwise reproducible and bitwise symmetric in x, y.
+//   * augLISI = 1 - P/S is finalised in double-float so the subtraction keeps
+//     the accuracy of the sums.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "iqa.h"
+
+namespace iqa {
+
+constexpr int kWave = 64;
+enum Mode : int { kLisi = 1, kAug = 2, kBoth = 3 };
+
+struct KArgs {
+    const float *x;
+    const float *y;
+    int64_t N;           // image side (row stride in floats)
+    int32_t NT;          // tile side
+    int32_t ns;          // tiles per side
+    int32_t ngx;         // tile groups along x: ceil(ns / ht)
+    int32_t log_seg;     // log2(lanes per segment)
+    int32_t log_grp;     // log2(lanes per tile in a wave) = log2(seg * rp)
+    int32_t ht;          // tiles per wave: 64 / (seg * rp)
+    int32_t ks;          // workgroups per tile group
+    int32_t rows_wave;   // tile rows per wave slice: NT / (waves * ks)
+    int32_t lpt;         // column groups per tile row: NT / vec
+    int32_t cpl;         // column chunks per lane: ceil(lpt / seg)
+    float D, C1, C2, C;
+    float *lisi;
+    float *aug;
+    float *sums;
+    float *ws;           // split partials: [group][ks][ht][4]
+};
+
+// ---------------------------------------------------------------------------
+// Compensated FP32 arithmetic
+// ---------------------------------------------------------------------------
+
+struct CSum {
+    float hi, lo;   // value = hi + lo
+};
+
+// Kahan step: add v, keeping in lo what the rounding of hi lost.
+__device__ __forceinline__ void cadd(CSum &a, float v) {
+    const float y = v + a.lo;
+    const float t = a.hi + y;
+    a.lo = y - (t - a.hi);
+    a.hi = t;
+}
+
+// Exact error-free sum s + e = a + b (Knuth's TwoSum; no ordering needed).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+struct Acc {
+    CSum A, P, X, Y;
+};
+
+__device__ __forceinline__ Acc acc_zero() {
+    return Acc{{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+}
+
+// ---------------------------------------------------------------------------
+// Lane permutations
+// ---------------------------------------------------------------------------
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Partner value for step `stride` of an all-reduce inside aligned groups of
+// 2*stride lanes.  Strides 1 and 2 swap within quads; 4 and 8 mirror within
+// half-rows / rows, which pairs every lane with the other half of its group
+// once the smaller strides have made each half uniform; 16 and 32 cross rows.
+__device__ __forceinline__ float partner(float v, int stride) {
+    switch (stride) {
+        case 1: return dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+        case 2: return dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+        case 4: return dpp<0x141>(v);   // row_half_mirror
+        case 8: return dpp<0x140>(v);   // row_mirror
+        default: return __shfl_xor(v, stride, kWave);
+    }
+}
+
+// Plain sums over aligned groups of 2^log_g lanes; every lane of a group ends
+// with the same bits (each step adds the same two values).
+struct Sum4 {
+    float A, P, X, Y;
+};
+
+template <int MODE>
+__device__ __forceinline__ Sum4 group_allreduce(Sum4 s, int log_g) {
+    for (int st = 1; st < (1 << log_g); st <<= 1) {
+        if constexpr ((MODE & kLisi) != 0) s.A += partner(s.A, st);
+        if constexpr ((MODE & kAug) != 0) s.P += partner(s.P, st);
+        s.X += partner(s.X, st);
+        s.Y += partner(s.Y, st);
+    }
+    return s;
+}
+
+__device__ __forceinline__ Sum4 fold(const Acc &a) {
+    return Sum4{a.A.hi + a.A.lo, a.P.hi + a.P.lo, a.X.hi + a.X.lo, a.Y.hi + a.Y.lo};
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel work
+// ---------------------------------------------------------------------------
+
+template <int VEC> struct VecT;
+template <> struct VecT<4> { using T = float4; };
+template <> struct VecT<2> { using T = float2; };
+template <> struct VecT<1> { using T = float; };
+
+template <int VEC>
+__device__ __forceinline__ typename VecT<VEC>::T vload(const float *p) {
+    return *reinterpret_cast<const typename VecT<VEC>::T *>(p);
+}
+
+template <int VEC>
+__device__ __forceinline__ typename VecT<VEC>::T vzero() {
+    typename VecT<VEC>::T z;
+    std::memset(&z, 0, sizeof(z));
+    return z;
+}
+
+template <int VEC>
+__device__ __forceinline__ float velem(const typename VecT<VEC>::T &v, int e) {
+    if constexpr (VEC == 1) {
+        return v;
+    } else {
+        return reinterpret_cast<const float *>(&v)[e];
+    }
+}
+
+// Fold VEC adjacent pixel pairs into a short plain-FP32 block, then add the
+// block into the compensated accumulators.  A pair of zeros (padding) adds
+// nothing.
+template <int VEC, int MODE>
+__device__ __forceinline__ void accumulate(const typename VecT<VEC>::T &xv,
+                                           const typename VecT<VEC>::T &yv,
+                                           float C1, Acc &acc) {
+    float bA = 0.f, bP = 0.f, bX = 0.f, bY = 0.f;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+        const float xr = velem<VEC>(xv, e);
+        const float yr = velem<VEC>(yv, e);
+        const float xc = xr > 0.f ? xr : 0.f;   // Sec. 2 clamp; NaN and -0 -> +0
+        const float yc = yr > 0.f ? yr : 0.f;
+        const float s = xc + yc;                // |x'+y'| (both non-negative)
+        const float d = fabsf(xc - yc);         // |x'-y'|
+        if constexpr ((MODE & kLisi) != 0) {
+            const float r = __builtin_amdgcn_rcpf(d + C1);
+            bA = (e == 0) ? s * r : __builtin_fmaf(s, r, bA);
+        }
+        if constexpr ((MODE & kAug) != 0) {
+            bP = (e == 0) ? s * d : __builtin_fmaf(s, d, bP);
+        }
+        bX = (e == 0) ? xc : bX + xc;
+        bY = (e == 0) ? yc : bY + yc;
+    }
+    if constexpr ((MODE & kLisi) != 0) cadd(acc.A, bA);
+    if constexpr ((MODE & kAug) != 0) cadd(acc.P, bP);
+    cadd(acc.X, bX);
+    cadd(acc.Y, bY);
+}
+
+// ---------------------------------------------------------------------------
+// Finalisation (Eq. 1, Eq. 2)
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+__device__ __forceinline__ void finalize(const KArgs &a, int64_t t, const Acc &acc) {
+    const float X1 = acc.X.hi + acc.X.lo;
+    const float Y1 = acc.Y.hi + acc.Y.lo;
+    if constexpr ((MODE & kLisi) != 0) {
+        if (a.lisi) {
+            const float A1 = acc.A.hi + acc.A.lo;
+            a.lisi[t] = (a.D * A1) / (fmaxf(X1, Y1) + a.C2);
+        }
+    }
+    if constexpr ((MODE & kAug) != 0) {
+        if (a.aug) {
+            // S = Sx + Sy + C and q = P / S in double-float, then 1 - q.
+            float s1, e1;
+            two_sum(acc.X.hi, acc.Y.hi, s1, e1);
+            const float lo1 = e1 + (acc.X.lo + acc.Y.lo);
+            float s2, e2;
+            two_sum(s1, a.C, s2, e2);
+            float Sh, Sl;
+            two_sum(s2, lo1 + e2, Sh, Sl);
+            float Ph, Pl;
+            two_sum(acc.P.hi, acc.P.lo, Ph, Pl);
+            const float q1 = Ph / Sh;
+            float r = __builtin_fmaf(-q1, Sh, Ph);     // exact remainder of Ph / Sh
+            r = __builtin_fmaf(-q1, Sl, r + Pl);
+            const float q2 = r / Sh;
+            float h, e;
+            two_sum(1.0f, -q1, h, e);
+            a.aug[t] = h + (e - q2);
+        }
+    }
+    if constexpr (MODE == kBoth) {
+        if (a.sums) {
+            float4 v;
+            v.x = acc.A.hi + acc.A.lo;
+            v.y = acc.P.hi + acc.P.lo;
+            v.z = X1;
+            v.w = Y1;
+            reinterpret_cast<float4 *>(a.sums)[t] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ Acc acc_of(const Sum4 &s) {
+    return Acc{{s.A, 0.f}, {s.P, 0.f}, {s.X, 0.f}, {s.Y, 0.f}};
+}
+
+// The dispatcher hands workgroup b to XCD b % 8, and each XCD has its own L2
+// whose channels interleave on low address bits.  Renumbering so that XCD x
+// gets one contiguous range of logical workgroups keeps every XCD streaming
+// from all column offsets (and so from all of its L2 channels) instead of the
+// one offset class that b % 8 would give it.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_remap(int b, int grid) {
+    const int xcd = b % kXcds;
+    const int local = b / kXcds;
+    const int full = grid / kXcds;
+    const int rem = grid % kXcds;
+    return xcd * full + (xcd < rem ? xcd : rem) + local;
+}
+
+// ---------------------------------------------------------------------------
+// The tile kernel
+// ---------------------------------------------------------------------------
+//
+// Grid: one workgroup of WAVES waves per (tile group, split part).  A tile
+// group is the ht = 64/(seg*rp) horizontally adjacent tiles one wave covers.
+// The tile's rows are cut into WAVES*ks contiguous slices of rows_wave rows;
+// wave w of part p takes slice p*WAVES + w.  Inside a wave, lane L works on
+// tile j = L >> log_grp of the group, row phase k = (L >> log_seg) & (rp-1) and
+// column group l = L & (seg-1): rows k, k+rp, k+2rp, ... of its slice.
+template <int VEC, int WAVES, int U, int MODE, bool WIDE>
+__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
+    using V = typename VecT<VEC>::T;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int seg = 1 << a.log_seg;
+    const int rp = 1 << (a.log_grp - a.log_seg);
+    const int l = lane & (seg - 1);
+    const int k = (lane >> a.log_seg) & (rp - 1);
+    const int j = lane >> a.log_grp;
+
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = bid / a.ks;
+    const int part = bid - grp * a.ks;
+    const int ty = grp / a.ngx;
+    const int txg = grp - ty * a.ngx;
+    const int tx = txg * a.ht + j;
+
+    const int slice = part * WAVES + wave;
+    int M = 0;   // rows of the tile this lane reduces
+    if (tx < a.ns && k < a.rows_wave) M = (a.rows_wave - k + rp - 1) / rp;
+    const int64_t row0 = (int64_t)ty * a.NT + (int64_t)slice * a.rows_wave + k;
+    const int64_t col0 = (int64_t)tx * a.NT;
+    const int64_t rstep = (int64_t)rp * a.N;
+
+    Acc acc = acc_zero();
+
+    if constexpr (!WIDE) {
+        // One column group per lane (lanes past the tile row idle), rows in
+        // batches of U, the next batch loading while this one is reduced.
+        if (l >= a.lpt) M = 0;
+        const float *px = a.x + row0 * a.N + col0 + (int64_t)l * VEC;
+        const float *py = a.y + row0 * a.N + col0 + (int64_t)l * VEC;
+        V ax[U], ay[U], bx[U], by[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (u < M) {
+                ax[u] = vload<VEC>(px + (int64_t)u * rstep);
+                ay[u] = vload<VEC>(py + (int64_t)u * rstep);
+            } else {
+                ax[u] = vzero<VEC>();
+                ay[u] = vzero<VEC>();
+            }
+        }
+        for (int m = 0; m < M; m += 2 * U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = m + U + u;
+                if (r < M) {
+                    bx[u] = vload<VEC>(px + (int64_t)r * rstep);
+                    by[u] = vload<VEC>(py + (int64_t)r * rstep);
+                } else {
+                    bx[u] = vzero<VEC>();
+                    by[u] = vzero<VEC>();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(ax[u], ay[u], a.C1, acc);
+            if (m + U >= M) break;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = m + 2 * U + u;
+                if (r < M) {
+                    ax[u] = vload<VEC>(px + (int64_t)r * rstep);
+                    ay[u] = vload<VEC>(py + (int64_t)r * rstep);
+                } else {
+                    ax[u] = vzero<VEC>();
+                    ay[u] = vzero<VEC>();
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(bx[u], by[u], a.C1, acc);
+        }
+    } else {
+        // Tile rows wider than a segment: chunk q covers column group l + q*seg.
+        for (int m = 0; m < M; ++m) {
+            const float *px = a.x + (row0 + (int64_t)m * rp) * a.N + col0;
+            const float *py = a.y + (row0 + (int64_t)m * rp) * a.N + col0;
+            for (int q0 = 0; q0 < a.cpl; q0 += U) {
+                V xv[U], yv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cg = l + (q0 + u) * seg;
+                    if (q0 + u < a.cpl && cg < a.lpt) {
+                        xv[u] = vload<VEC>(px + (int64_t)cg * VEC);
+                        yv[u] = vload<VEC>(py + (int64_t)cg * VEC);
+                    } else {
+                        xv[u] = vzero<VEC>();
+                        yv[u] = vzero<VEC>();
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(xv[u], yv[u], a.C1, acc);
+            }
+        }
+    }
+
+    // Sum the lanes of each tile inside the wave.
+    const Sum4 s = group_allreduce<MODE>(fold(acc), a.log_grp);
+    const bool leader = (lane & ((1 << a.log_grp) - 1)) == 0;
+
+    if constexpr (WAVES == 1) {
+        if (!leader || tx >= a.ns) return;
+        if (a.ks == 1) {
+            finalize<MODE>(a, (int64_t)ty * a.ns + tx, acc_of(s));
+        } else {
+            float4 v{s.A, s.P, s.X, s.Y};
+            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + j] = v;
+        }
+    } else {
+        // Combine the waves' slices of each tile in LDS, wave order fixed.
+        __shared__ float4 lds[WAVES][kWave];
+        if (leader) lds[wave][j] = float4{s.A, s.P, s.X, s.Y};
+        __syncthreads();
+        if (wave != 0 || lane >= a.ht) return;
+        const int txl = txg * a.ht + lane;
+        if (txl >= a.ns) return;
+        Acc c = acc_zero();
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const float4 v = lds[w][lane];
+            if constexpr ((MODE & kLisi) != 0) cadd(c.A, v.x);
+            if constexpr ((MODE & kAug) != 0) cadd(c.P, v.y);
+            cadd(c.X, v.z);
+            cadd(c.Y, v.w);
+        }
+        if (a.ks == 1) {
+            finalize<MODE>(a, (int64_t)ty * a.ns + txl, c);
+        } else {
+            float4 v{c.A.hi + c.A.lo, c.P.hi + c.P.lo, c.X.hi + c.X.lo, c.Y.hi + c.Y.lo};
+            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + lane] = v;
+        }
+    }
+}
+
+// Split tiles: one thread per tile adds the ks parts' partial sums in part
+// order and finalises.  Runs after tiles_kernel on the same stream, so the
+// partials are complete and visible.
+template <int MODE>
+__global__ __launch_bounds__(256) void combine_kernel(KArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)a.ns * a.ns;
+    if (t >= n) return;
+    const int64_t ty = t / a.ns;
+    const int64_t tx = t - ty * a.ns;
+    const int64_t grp = ty * a.ngx + tx / a.ht;
+    const int64_t j = tx % a.ht;
+    Acc c = acc_zero();
+    const float4 *ws = reinterpret_cast<const float4 *>(a.ws);
+    for (int p = 0; p < a.ks; ++p) {
+        const float4 v = ws[(grp * a.ks + p) * a.ht + j];
+        if constexpr ((MODE & kLisi) != 0) cadd(c.A, v.x);
+        if constexpr ((MODE & kAug) != 0) cadd(c.P, v.y);
+        cadd(c.X, v.z);
+        cadd(c.Y, v.w);
+    }
+    finalize<MODE>(a, t, c);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming-read reference: the attainable HBM read rate on this GPU
+// ---------------------------------------------------------------------------
+//
+// Each workgroup sums a contiguous chunk of float4s (several loads in flight
+// per lane) and writes one float; the result is only there so that the loads
+// cannot be removed.  Used to express the tile kernel's bandwidth as a
+// fraction of what a plain read achieves.
+__global__ __launch_bounds__(256) void read_ceiling_kernel(const float4 *__restrict__ src,
+                                                           int64_t n4, int64_t per_block,
+                                                           float *out) {
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = b0 + per_block < n4 ? b0 + per_block : n4;
+    float acc = 0.f;
+    int64_t i = b0 + threadIdx.x;
+    for (; i + 3 * 256 < b1; i += 4 * 256) {
+        const float4 a = src[i], b = src[i + 256], c = src[i + 512], d = src[i + 768];
+        acc += (a.x + a.y + a.z + a.w) + (b.x + b.y + b.z + b.w) +
+               (c.x + c.y + c.z + c.w) + (d.x + d.y + d.z + d.w);
+    }
+    for (; i < b1; i += 256) {
+        const float4 a = src[i];
+        acc += a.x + a.y + a.z + a.w;
+    }
+    for (int st = 32; st > 0; st >>= 1) acc += __shfl_xor(acc, st, kWave);
+    __shared__ float part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+thread_local int g_last_hip_error = 0;
+
+using LaunchFn = void (*)(const KArgs &, unsigned, hipStream_t);
+
+template <int VEC, int WAVES, int U, int MODE, bool WIDE>
+void launch_impl(const KArgs &a, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((tiles_kernel<VEC, WAVES, U, MODE, WIDE>), dim3(grid),
+                       dim3(WAVES * kWave), 0, s, a);
+}
+
+template <int VEC, int WAVES, int U, bool WIDE>
+LaunchFn pick_mode(int mode) {
+    switch (mode) {
+        case kLisi: return &launch_impl<VEC, WAVES, U, kLisi, WIDE>;
+        case kAug: return &launch_impl<VEC, WAVES, U, kAug, WIDE>;
+        default: return &launch_impl<VEC, WAVES, U, kBoth, WIDE>;
+    }
+}
+
+template <int VEC, int WAVES, int U>
+LaunchFn pick_wide(int mode, bool wide) {
+    return wide ? pick_mode<VEC, WAVES, U, true>(mode) : pick_mode<VEC, WAVES, U, false>(mode);
+}
+
+template <int VEC, int WAVES>
+LaunchFn pick_unroll(int unroll, int mode, bool wide) {
+    switch (unroll) {
+        case 4: return pick_wide<VEC, WAVES, 4>(mode, wide);
+        case 8: return pick_wide<VEC, WAVES, 8>(mode, wide);
+        default: return nullptr;
+    }
+}
+
+// The instantiated launch shapes: waves 1/2/4/8 with unroll 4/8 for vec 4,
+// and waves 1/4 with unroll 4 for the narrow vec 2 and vec 1 paths.
+LaunchFn pick(const iqa_launch_cfg &c, int mode, bool wide) {
+    if (c.vec == 4) {
+        switch (c.waves) {
+            case 1: return pick_unroll<4, 1>(c.unroll, mode, wide);
+            case 2: return pick_unroll<4, 2>(c.unroll, mode, wide);
+            case 4: return pick_unroll<4, 4>(c.unroll, mode, wide);
+            case 8: return pick_unroll<4, 8>(c.unroll, mode, wide);
+            default: return nullptr;
+        }
+    }
+    if (c.unroll != 4 || !(c.waves == 1 || c.waves == 4)) return nullptr;
+    if (c.vec == 2) return c.waves == 1 ? pick_wide<2, 1, 4>(mode, wide) : pick_wide<2, 4, 4>(mode, wide);
+    if (c.vec == 1) return c.waves == 1 ? pick_wide<1, 1, 4>(mode, wide) : pick_wide<1, 4, 4>(mode, wide);
+    return nullptr;
+}
+
+void launch_combine(const KArgs &a, int mode, hipStream_t s) {
+    const int64_t n = (int64_t)a.ns * a.ns;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    switch (mode) {
+        case kLisi:
+            hipLaunchKernelGGL(combine_kernel<kLisi>, dim3(blocks), dim3(256), 0, s, a);
+            break;
+        case kAug:
+            hipLaunchKernelGGL(combine_kernel<kAug>, dim3(blocks), dim3(256), 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL(combine_kernel<kBoth>, dim3(blocks), dim3(256), 0, s, a);
+            break;
+    }
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+int64_t next_pow2(int64_t v) { return int64_t(1) << ilog2(v); }
+
+bool param_ok(float v) {
+    return std::isfinite(v) && v > 0.f && std::fpclassify(v) == FP_NORMAL;
+}
+
+bool aligned(const void *p, size_t b) { return (reinterpret_cast<uintptr_t>(p) % b) == 0; }
+
+iqa_status check_shape(int64_t N, int64_t NT) {
+    if (N <= 0 || NT <= 0 || N > IQA_MAX_N || NT > N || N % NT != 0) return IQA_ERR_SHAPE;
+    return IQA_OK;
+}
+
+struct Geometry {
+    int64_t ns, ht, ngx, groups, grid;
+    int lpt, cpl;
+};
+
+iqa_status geometry(int64_t N, int64_t NT, const iqa_launch_cfg &c, Geometry &g) {
+    if (!(c.vec == 1 || c.vec == 2 || c.vec == 4) || NT % c.vec) return IQA_ERR_CONFIG;
+    if (!is_pow2(c.seg) || !is_pow2(c.rp) || (int64_t)c.seg * c.rp > kWave) return IQA_ERR_CONFIG;
+    if (!is_pow2(c.waves) || c.waves > 8) return IQA_ERR_CONFIG;
+    if (c.ksplit < 1 || NT % ((int64_t)c.waves * c.ksplit) != 0) return IQA_ERR_CONFIG;
+    if (pick(c, kBoth, false) == nullptr) return IQA_ERR_CONFIG;
+    g.ns = N / NT;
+    g.ht = kWave / ((int64_t)c.seg * c.rp);
+    g.ngx = (g.ns + g.ht - 1) / g.ht;
+    g.groups = g.ns * g.ngx;
+    g.grid = g.groups * c.ksplit;
+    g.lpt = (int)(NT / c.vec);
+    g.cpl = (int)((g.lpt + c.seg - 1) / c.seg);
+    if (g.grid > (int64_t)INT_MAX) return IQA_ERR_CONFIG;
+    return IQA_OK;
+}
+
+// Built-in launch shape for (N, NT): widest aligned vector, one segment per
+// tile row (up to a full wave), as many tiles per wave as keep >= kTarget
+// waves in flight, then row splits across waves and workgroups if the tiles
+// are still too few.
+constexpr int64_t kTargetWaves = 2048;   // 8 per CU on 256 CUs
+
+iqa_launch_cfg default_cfg(int64_t N, int64_t NT, const float *x, const float *y) {
+    iqa_launch_cfg c{};
+    c.vec = 1;
+    if (NT % 2 == 0 && aligned(x, 8) && aligned(y, 8)) c.vec = 2;
+    if (NT % 4 == 0 && aligned(x, 16) && aligned(y, 16)) c.vec = 4;
+    c.unroll = c.vec == 4 ? 8 : 4;
+    const int64_t lpt = NT / c.vec;
+    c.seg = (int)std::min<int64_t>(kWave, next_pow2(lpt));
+    const int64_t tpw = kWave / c.seg;     // segments per wave
+    const int64_t ns = N / NT;
+    // Tiles per wave (ht = tpw / rp): start wide, narrow while too few waves
+    // and each segment keeps >= 8 rows.
+    int64_t rp = 1;
+    while (rp < tpw) {
+        const int64_t ht = tpw / rp;
+        const int64_t waves = ns * ((ns + ht - 1) / ht);
+        if (waves >= kTargetWaves || NT / (rp * 2) < 8) break;
+        rp *= 2;
+    }
+    c.rp = (int)rp;
+    const int64_t ht = tpw / rp;
+    const int64_t groups = ns * ((ns + ht - 1) / ht);
+    int64_t kw = 1;
+    while (kw < 8 && groups * kw < kTargetWaves && NT % (kw * 2) == 0 && NT / (rp * kw * 2) >= 8)
+        kw *= 2;
+    if (c.vec != 4 && kw > 1) kw = (NT % 4 == 0) ? 4 : 1;
+    int64_t ks = 1;
+    while (groups * kw * ks < kTargetWaves && NT % (kw * ks * 2) == 0 &&
+           NT / (rp * kw * ks * 2) >= 8)
+        ks *= 2;
+    c.waves = (int)kw;
+    c.ksplit = (int)ks;
+    return c;
+}
+
+// Per (device, stream) workspace for split partials.  Partials are written by
+// tiles_kernel and read by combine_kernel in the same stream order, so one
+// buffer per stream is enough; concurrent streams get their own.
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mutex;
+std::map<std::pair<int, void *>, Workspace> g_ws;
+
+iqa_status workspace_for(hipStream_t s, size_t bytes, float **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return IQA_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    Workspace &w = g_ws[{dev, (void *)s}];
+    if (w.bytes < bytes) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (s != nullptr) {
+            e = hipStreamIsCapturing(s, &cs);
+            if (e != hipSuccess) {
+                g_last_hip_error = (int)e;
+                return IQA_ERR_HIP;
+            }
+        }
+        if (cs != hipStreamCaptureStatusNone) return IQA_ERR_CAPTURE;
+        const size_t nb = (std::max(bytes, w.bytes) + 4095) & ~size_t(4095);
+        void *p = nullptr;
+        e = hipMalloc(&p, nb);
+        if (e != hipSuccess) {
+            g_last_hip_error = (int)e;
+            return IQA_ERR_HIP;
+        }
+        if (w.ptr) {
+            // Earlier launches on this stream may still use the old buffer.
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(w.ptr);
+        }
+        w.ptr = p;
+        w.bytes = nb;
+    }
+    *out = static_cast<float *>(w.ptr);
+    return IQA_OK;
+}
+
+iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
+               float C2, float C, float *lisi, float *aug, float *sums,
+               const iqa_launch_cfg *cfg_in, void *stream, bool prepare_only) {
+    iqa_launch_cfg c = cfg_in ? *cfg_in : default_cfg(N, NT, x, y);
+    Geometry g{};
+    iqa_status st = geometry(N, NT, c, g);
+    if (st != IQA_OK) return st;
+    if (!prepare_only) {
+        if (!aligned(x, 4 * c.vec) || !aligned(y, 4 * c.vec)) return IQA_ERR_ALIGN;
+    }
+    int mode = ((lisi || sums) ? kLisi : 0) | ((aug || sums) ? kAug : 0);
+    if (mode == 0) mode = kBoth;
+    const bool wide = g.cpl > 1;
+    LaunchFn fn = pick(c, mode, wide);
+    if (!fn) return IQA_ERR_CONFIG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    KArgs a{};
+    if (c.ksplit > 1) {
+        const size_t bytes = (size_t)g.groups * c.ksplit * g.ht * 4 * sizeof(float);
+        st = workspace_for(s, bytes, &a.ws);
+        if (st != IQA_OK) return st;
+    }
+    if (prepare_only) return IQA_OK;
+
+    a.x = x;
+    a.y = y;
+    a.N = N;
+    a.NT = (int32_t)NT;
+    a.ns = (int32_t)g.ns;
+    a.ngx = (int32_t)g.ngx;
+    a.log_seg = ilog2(c.seg);
+    a.log_grp = ilog2((int64_t)c.seg * c.rp);
+    a.ht = (int32_t)g.ht;
+    a.ks = c.ksplit;
+    a.rows_wave = (int32_t)(NT / ((int64_t)c.waves * c.ksplit));
+    a.lpt = g.lpt;
+    a.cpl = g.cpl;
+    a.D = D;
+    a.C1 = C1;
+    a.C2 = C2;
+    a.C = C;
+    a.lisi = lisi;
+    a.aug = aug;
+    a.sums = sums;
+    fn(a, (unsigned)g.grid, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && c.ksplit > 1) {
+        launch_combine(a, mode, s);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return IQA_ERR_HIP;
+    }
+    return IQA_OK;
+}
+
+iqa_status check_common(const float *x, const float *y, int64_t N, int64_t NT) {
+    if (!x || !y) return IQA_ERR_NULL;
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    if (!aligned(x, 4) || !aligned(y, 4)) return IQA_ERR_ALIGN;
+    return IQA_OK;
+}
+
+}  // namespace iqa
+
+using namespace iqa;
+
+extern "C" {
+
+iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT, float D,
+                         float C1, float C2, float C, float *lisi, float *auglisi, float *sums,
+                         const iqa_launch_cfg *cfg, void *stream) {
+    iqa_status st = check_common(x, y, N, NT);
+    if (st != IQA_OK) return st;
+    if (!lisi && !auglisi && !sums) return IQA_ERR_NULL;
+    if (!aligned(lisi, 4) || !aligned(auglisi, 4) || !aligned(sums, 16)) return IQA_ERR_ALIGN;
+    const bool need_l = lisi || sums, need_a = auglisi || sums;
+    if (need_l && (!param_ok(D) || !param_ok(C1) || !param_ok(C2))) return IQA_ERR_PARAM;
+    if (need_a && !param_ok(C)) return IQA_ERR_PARAM;
+    return run(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, cfg, stream, false);
+}
+
+iqa_status iqa_tiles(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
+                     float C2, float C, float *lisi, float *auglisi, float *sums, void *stream) {
+    return iqa_tiles_cfg(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, nullptr, stream);
+}
+
+iqa_status lisi_tiles(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
+                      float C2, float *lisi, void *stream) {
+    iqa_status st = check_common(x, y, N, NT);
+    if (st != IQA_OK) return st;
+    if (!lisi) return IQA_ERR_NULL;
+    if (!aligned(lisi, 4)) return IQA_ERR_ALIGN;
+    if (!param_ok(D) || !param_ok(C1) || !param_ok(C2)) return IQA_ERR_PARAM;
+    return run(x, y, N, NT, D, C1, C2, 1.0f, lisi, nullptr, nullptr, nullptr, stream, false);
+}
+
+iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT, float C,
+                         float *auglisi, void *stream) {
+    iqa_status st = check_common(x, y, N, NT);
+    if (st != IQA_OK) return st;
+    if (!auglisi) return IQA_ERR_NULL;
+    if (!aligned(auglisi, 4)) return IQA_ERR_ALIGN;
+    if (!param_ok(C)) return IQA_ERR_PARAM;
+    return run(x, y, N, NT, 1.0f, 1.0f, 1.0f, C, nullptr, auglisi, nullptr, nullptr, stream,
+               false);
+}
+
+iqa_status iqa_default_cfg(int64_t N, int64_t NT, const float *x, const float *y,
+                           iqa_launch_cfg *cfg) {
+    if (!cfg) return IQA_ERR_NULL;
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    *cfg = default_cfg(N, NT, x, y);
+    return IQA_OK;
+}
+
+iqa_status iqa_check_cfg(int64_t N, int64_t NT, const iqa_launch_cfg *cfg) {
+    if (!cfg) return IQA_ERR_NULL;
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    Geometry g{};
+    return geometry(N, NT, *cfg, g);
+}
+
+iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *stream) {
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    const float *probe = reinterpret_cast<const float *>(uintptr_t(256));
+    return run(probe, probe, N, NT, 1.f, 1.f, 1.f, 1.f, nullptr, nullptr, nullptr, cfg, stream,
+               true);
+}
+
+iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blocks,
+                            void *stream) {
+    if (!buf || !out) return IQA_ERR_NULL;
+    if (n <= 0 || n % 4 != 0 || blocks <= 0 || blocks > INT_MAX) return IQA_ERR_SHAPE;
+    if (!aligned(buf, 16) || !aligned(out, 4)) return IQA_ERR_ALIGN;
+    const int64_t n4 = n / 4;
+    const int64_t per = (n4 + blocks - 1) / blocks;
+    hipLaunchKernelGGL(read_ceiling_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(buf),
+                       n4, per, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return IQA_ERR_HIP;
+    }
+    return IQA_OK;
+}
+
+const char *iqa_status_str(int status) {
+    switch (status) {
+        case IQA_OK: return "IQA_OK";
+        case IQA_ERR_NULL: return "IQA_ERR_NULL: a required pointer is NULL or no output was requested";
+        case IQA_ERR_SHAPE: return "IQA_ERR_SHAPE: N and NT must be positive, NT must divide N, N <= 2^17";
+        case IQA_ERR_ALIGN: return "IQA_ERR_ALIGN: a float pointer is not 4-byte aligned (sums: 16-byte)";
+        case IQA_ERR_PARAM: return "IQA_ERR_PARAM: D, C1, C2 and C must be positive, finite, normal floats";
+        case IQA_ERR_HIP: return "IQA_ERR_HIP: a HIP call or kernel launch failed";
+        case IQA_ERR_CONFIG: return "IQA_ERR_CONFIG: launch configuration invalid for this shape";
+        case IQA_ERR_CAPTURE: return "IQA_ERR_CAPTURE: workspace must grow while the stream is captured";
+        default: return "unknown iqa_status";
+    }
+}
+
+int iqa_last_hip_error(void) { return g_last_hip_error; }
+
+int iqa_version(void) { return 200; }
+
+}  // extern "C"

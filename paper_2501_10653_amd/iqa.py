@@ -1,0 +1,166 @@
+"""Python binding of the tile-wise LISI / augLISI library.
+
+Argument marshalling only: tensors are checked, outputs are allocated with
+torch on the inputs' device, and the C entry points of ``libiqa_hip.so`` do
+all of the work on the caller's (or torch's current) HIP stream.  The names
+mirror the C ABI: :func:`iqa_tiles`, :func:`lisi_tiles`, :func:`auglisi_tiles`.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, NamedTuple, Optional
+
+import torch
+
+from . import _lib
+from ._lib import IqaError, LaunchCfg
+
+# The paper only asks C1, C2, C << 1; these defaults are 1e-6 each and D is
+# C1/2, the choice for which identical tiles give LISI = S/(S + C2) ~ 1.
+C_DEFAULT = 1e-6
+
+
+def default_D(C1: float) -> float:
+    """D = C1/2, computed on the float32 value of C1."""
+    import numpy as np
+    return float(np.float32(C1)) / 2.0
+
+
+class TileResult(NamedTuple):
+    lisi: Optional[torch.Tensor]
+    auglisi: Optional[torch.Tensor]
+    sums: Optional[torch.Tensor]
+
+
+def _check_images(x: torch.Tensor, y: torch.Tensor) -> int:
+    for name, t in (("x", x), ("y", y)):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must live on a HIP device, got {t.device}")
+        if t.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32, got {t.dtype}")
+        if t.dim() != 2 or t.shape[0] != t.shape[1]:
+            raise ValueError(f"{name} must be N x N, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous (row-major)")
+    if x.shape != y.shape or x.device != y.device:
+        raise ValueError("x and y must have the same shape and device")
+    return int(x.shape[0])
+
+
+def _stream_handle(device: torch.device, stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _out(shape, device, given: Optional[torch.Tensor], name: str) -> torch.Tensor:
+    if given is None:
+        return torch.empty(shape, dtype=torch.float32, device=device)
+    if tuple(given.shape) != tuple(shape) or given.dtype != torch.float32 or \
+            not given.is_contiguous() or given.device != device:
+        raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shape} on {device}")
+    return given
+
+
+def iqa_tiles(x: torch.Tensor, y: torch.Tensor, NT: int, *, C1: float = C_DEFAULT,
+              C2: float = C_DEFAULT, C: float = C_DEFAULT, D: Optional[float] = None,
+              lisi: bool = True, auglisi: bool = True, sums: bool = False,
+              cfg: Optional[dict] = None, stream=None,
+              out: Optional[Dict[str, torch.Tensor]] = None) -> TileResult:
+    """Fused per-tile LISI (Eq. 1) and augLISI (Eq. 2) of two N x N images.
+
+    Returns (N/NT, N/NT) float32 matrices (row-major tiles) and, when asked,
+    the (n, 4) per-tile sums A, P, Sx, Sy.  Work is enqueued on ``stream``
+    (default: torch's current stream) and not waited for."""
+    N = _check_images(x, y)
+    if D is None:
+        D = default_D(C1)
+    out = out or {}
+    ns = N // NT if NT > 0 and N % NT == 0 else 0
+    dev = x.device
+    lo = _out((ns, ns), dev, out.get("lisi"), "lisi") if lisi else None
+    ao = _out((ns, ns), dev, out.get("auglisi"), "auglisi") if auglisi else None
+    so = _out((ns * ns, 4), dev, out.get("sums"), "sums") if sums else None
+    lib = _lib.load()
+    cfg_p = ctypes.byref(LaunchCfg.from_dict(cfg)) if cfg is not None else None
+    with torch.cuda.device(dev):
+        st = lib.iqa_tiles_cfg(_ptr(x), _ptr(y), N, NT, D, C1, C2, C, _ptr(lo), _ptr(ao),
+                               _ptr(so), cfg_p, _stream_handle(dev, stream))
+    _lib.check(st, "iqa_tiles")
+    return TileResult(lo, ao, so)
+
+
+def lisi_tiles(x: torch.Tensor, y: torch.Tensor, NT: int, *, C1: float = C_DEFAULT,
+               C2: float = C_DEFAULT, D: Optional[float] = None, stream=None,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-tile LISI (Eq. 1) only; bitwise equal to iqa_tiles' LISI output."""
+    N = _check_images(x, y)
+    if D is None:
+        D = default_D(C1)
+    ns = N // NT if NT > 0 and N % NT == 0 else 0
+    lo = _out((ns, ns), x.device, out, "out")
+    with torch.cuda.device(x.device):
+        st = _lib.load().lisi_tiles(_ptr(x), _ptr(y), N, NT, D, C1, C2, _ptr(lo),
+                                    _stream_handle(x.device, stream))
+    _lib.check(st, "lisi_tiles")
+    return lo
+
+
+def auglisi_tiles(x: torch.Tensor, y: torch.Tensor, NT: int, *, C: float = C_DEFAULT,
+                  stream=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-tile augLISI (Eq. 2) only; bitwise equal to iqa_tiles' output."""
+    N = _check_images(x, y)
+    ns = N // NT if NT > 0 and N % NT == 0 else 0
+    ao = _out((ns, ns), x.device, out, "out")
+    with torch.cuda.device(x.device):
+        st = _lib.load().auglisi_tiles(_ptr(x), _ptr(y), N, NT, C, _ptr(ao),
+                                       _stream_handle(x.device, stream))
+    _lib.check(st, "auglisi_tiles")
+    return ao
+
+
+def default_cfg(N: int, NT: int, x: Optional[torch.Tensor] = None,
+                y: Optional[torch.Tensor] = None) -> dict:
+    """The launch configuration iqa_tiles picks for (N, NT) (and the images'
+    alignment; 256-byte aligned pointers are assumed when none are given)."""
+    c = LaunchCfg()
+    px = _ptr(x) if x is not None else 256
+    py = _ptr(y) if y is not None else 256
+    _lib.check(_lib.load().iqa_default_cfg(N, NT, px, py, ctypes.byref(c)), "iqa_default_cfg")
+    return c.as_dict()
+
+
+def check_cfg(N: int, NT: int, cfg: dict) -> int:
+    """Status of an explicit configuration for (N, NT): 0 when valid."""
+    return int(_lib.load().iqa_check_cfg(N, NT, ctypes.byref(LaunchCfg.from_dict(cfg))))
+
+
+def prepare(N: int, NT: int, cfg: Optional[dict] = None, stream=None,
+            device: Optional[torch.device] = None) -> None:
+    """Allocate the split workspace (N, NT, cfg) needs on ``stream`` ahead of
+    graph capture."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    cfg_p = ctypes.byref(LaunchCfg.from_dict(cfg)) if cfg is not None else None
+    with torch.cuda.device(device):
+        st = _lib.load().iqa_prepare(N, NT, cfg_p, _stream_handle(device, stream))
+    _lib.check(st, "iqa_prepare")
+
+
+def read_ceiling(buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    """Streaming-read reference kernel (measurement only): one float per
+    workgroup into ``out``; the number of workgroups is ``out.numel()``."""
+    if buf.dtype != torch.float32 or not buf.is_contiguous() or out.dtype != torch.float32:
+        raise ValueError("read_ceiling needs contiguous float32 tensors")
+    with torch.cuda.device(buf.device):
+        st = _lib.load().iqa_read_ceiling(buf.data_ptr(), buf.numel(), out.data_ptr(),
+                                          out.numel(), _stream_handle(buf.device, stream))
+    _lib.check(st, "iqa_read_ceiling")

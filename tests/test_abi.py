@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+that include/iqa.h declares, and rejects bad arguments before any HIP call."""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2501_10653_amd import _lib
+from paper_2501_10653_amd._lib import LaunchCfg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "iqa.h")
+
+OK, NULL, SHAPE, ALIGN, PARAM, HIP, CONFIG, CAPTURE = range(8)
+FAKE = 1 << 20          # 16-byte-aligned stand-in for a device pointer (never dereferenced)
+C6 = 1e-6
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[a-z_ *]*?\b([a-z_]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("iqa_tiles", "lisi_tiles", "auglisi_tiles", "iqa_status_str"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(declared_functions()) <= exported
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for s in range(8):
+        assert lib.iqa_status_str(s).decode().startswith(_lib.STATUS_NAMES[s])
+    assert b"unknown" in lib.iqa_status_str(99)
+    assert lib.iqa_version() >= 100
+
+
+def call_tiles(x=FAKE, y=FAKE, N=2048, NT=64, D=C6 / 2, C1=C6, C2=C6, C=C6, lisi=FAKE,
+               aug=FAKE, sums=None):
+    return _lib.load().iqa_tiles(x, y, N, NT, D, C1, C2, C, lisi, aug, sums, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(x=None), NULL), (dict(y=None), NULL), (dict(lisi=None, aug=None), NULL),
+    (dict(N=0), SHAPE), (dict(NT=0), SHAPE), (dict(N=-4, NT=2), SHAPE), (dict(N=100, NT=7), SHAPE),
+    (dict(N=64, NT=128), SHAPE), (dict(N=(1 << 17) + 2, NT=2), SHAPE),
+    (dict(x=FAKE + 2), ALIGN), (dict(lisi=FAKE + 1), ALIGN), (dict(sums=FAKE + 4), ALIGN),
+    (dict(C1=0.0), PARAM), (dict(C2=-1.0), PARAM), (dict(C=float("nan")), PARAM),
+    (dict(D=float("inf")), PARAM), (dict(C1=1e-40), PARAM), (dict(D=0.0), PARAM),
+])
+def test_validation_before_launch(kw, status):
+    assert call_tiles(**kw) == status
+
+
+def test_split_entry_points_validate_only_their_constants():
+    lib = _lib.load()
+    # lisi_tiles ignores C, auglisi_tiles ignores D, C1, C2: only their own are checked
+    assert lib.lisi_tiles(FAKE, FAKE, 64, 8, 0.5, 0.0, C6, FAKE, None) == PARAM
+    assert lib.lisi_tiles(FAKE, FAKE, 64, 8, 0.5, C6, C6, None, None) == NULL
+    assert lib.auglisi_tiles(FAKE, FAKE, 64, 8, 0.0, FAKE, None) == PARAM
+    assert lib.auglisi_tiles(FAKE, None, 64, 8, C6, FAKE, None) == NULL
+    assert lib.auglisi_tiles(FAKE, FAKE, 64, 7, C6, FAKE, None) == SHAPE
+
+
+def default_cfg(N, NT, x=FAKE, y=FAKE):
+    c = LaunchCfg()
+    st = _lib.load().iqa_default_cfg(N, NT, x, y, ctypes.byref(c))
+    return st, c.as_dict()
+
+
+@pytest.mark.parametrize("N,NT", [(256, 32), (2048, 64), (1024, 256), (8192, 16), (4096, 128),
+                                  (12, 3), (10, 10), (300, 12), (1000, 8), (7, 1), (1, 1),
+                                  (512, 512), (8192, 8192), (6, 2)])
+def test_default_cfg_is_valid(N, NT):
+    st, c = default_cfg(N, NT)
+    assert st == OK
+    assert NT % c["vec"] == 0
+    assert _lib.load().iqa_check_cfg(N, NT, ctypes.byref(LaunchCfg.from_dict(c))) == OK
+
+
+def test_default_cfg_follows_alignment():
+    assert default_cfg(64, 8, FAKE + 8, FAKE)[1]["vec"] == 2
+    assert default_cfg(64, 8, FAKE + 4, FAKE)[1]["vec"] == 1
+    assert default_cfg(66, 6, FAKE, FAKE)[1]["vec"] == 2
+    assert default_cfg(63, 9, FAKE, FAKE)[1]["vec"] == 1
+    assert default_cfg(64, 9)[0] == SHAPE
+
+
+@pytest.mark.parametrize("bad", [
+    dict(vec=3), dict(vec=4, waves=3), dict(waves=16), dict(seg=12), dict(seg=128), dict(rp=3),
+    dict(seg=16, rp=8), dict(ksplit=0), dict(ksplit=3), dict(vec=2, waves=2),
+    dict(vec=1, unroll=8), dict(unroll=16), dict(unroll=2), dict(waves=8, ksplit=16),
+])
+def test_check_cfg_rejects(bad):
+    base = dict(vec=4, waves=1, unroll=8, seg=16, rp=4, ksplit=1)
+    base.update(bad)
+    st = _lib.load().iqa_check_cfg(2048, 64, ctypes.byref(LaunchCfg.from_dict(base)))
+    assert st == CONFIG
+
+
+def test_cfg_call_rejects_invalid_config_before_launch():
+    bad = LaunchCfg.from_dict(dict(vec=4, waves=5, unroll=4, seg=16, rp=1, ksplit=1))
+    st = _lib.load().iqa_tiles_cfg(FAKE, FAKE, 2048, 64, C6 / 2, C6, C6, C6, FAKE, None, None,
+                                   ctypes.byref(bad), None)
+    assert st == CONFIG
