@@ -121,8 +121,8 @@ iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT,
  * while the previous `unroll` are reduced. */
 typedef struct iqa_launch_cfg {
     int32_t vec;     /* floats per lane load: 4, 2 or 1; NT % vec == 0 */
-    int32_t waves;   /* waves per workgroup: 1, 2, 4 or 8 (vec 4); 1 or 4 (vec 1, 2) */
-    int32_t unroll;  /* rows per load batch: 4 or 8 (vec 4); 4 (vec 1, 2) */
+    int32_t waves;   /* waves per workgroup: 1, 2, 4, 8 or 16 (vec 4); 1 or 4 (vec 1, 2) */
+    int32_t unroll;  /* rows per load batch: 4 or 8 (vec 4, waves <= 8); 4 otherwise */
     int32_t seg;     /* lanes per tile row segment: power of two, 1..64 */
     int32_t rp;      /* row phases per tile in a wave: power of two, seg*rp <= 64 */
     int32_t ksplit;  /* workgroups per tile group: >= 1; NT % (waves*ksplit) == 0 */
@@ -149,6 +149,70 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT,
  * default) needs on `stream`, so that later calls allocate nothing (e.g.
  * under graph capture).  IQA_OK when nothing or everything was allocated. */
 iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tuned launch shapes                                                       */
+/* ------------------------------------------------------------------------ */
+
+#define IQA_TUNE_SINGLE 0   /* shape used by iqa_tiles & co. for (N, NT) */
+#define IQA_TUNE_BATCH 1    /* per-pair geometry inside iqa_tiles_batched */
+
+/* Register a measured-best launch configuration for (N, NT), replacing the
+ * built-in choice.  Single-pair entries are used when both images are
+ * 16-byte aligned; batch entries must have vec 4, waves 1, ksplit 1 and
+ * unroll 8.  IQA_ERR_CONFIG if cfg is invalid for the shape.  Thread-safe;
+ * takes effect for calls made after it returns. */
+iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *cfg);
+
+/* Forget every registered configuration. */
+void iqa_tune_clear(void);
+
+/* ------------------------------------------------------------------------ */
+/* Ragged batches: many image pairs of mixed N and N_T in one launch         */
+/* ------------------------------------------------------------------------ */
+
+/* One image pair of a batch: the arguments of iqa_tiles for that pair. */
+typedef struct iqa_pair {
+    const float *x;
+    const float *y;
+    int64_t N;
+    int64_t NT;
+    float D, C1, C2, C;
+    float *lisi;
+    float *auglisi;
+    float *sums;
+} iqa_pair;
+
+/* Bytes of one opaque per-pair batch descriptor. */
+#define IQA_BATCH_DESC_BYTES 128
+
+/* The per-pair geometry a batch uses for (N, NT) (NT % 4 == 0).  A pair's
+ * batched results are bitwise equal to iqa_tiles_cfg with this config. */
+iqa_status iqa_batch_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg);
+
+/* Host-side planning of a batch (no GPU calls).
+ *   pairs        host array of `count` pairs; each is validated as iqa_tiles
+ *                would, and must also have NT % 4 == 0 (IQA_ERR_CONFIG) and
+ *                16-byte aligned images (IQA_ERR_ALIGN).
+ *   descs        host buffer of count * IQA_BATCH_DESC_BYTES bytes, filled
+ *                with opaque descriptors that embed the device pointers.
+ *   total_units  receives the number of work units (tile groups) in all.
+ * The caller copies `descs` to device memory (16-byte aligned) unchanged and
+ * passes that copy to iqa_tiles_batched; it stays valid as long as the pairs'
+ * buffers do, so one copy can be launched (or graph-replayed) many times. */
+iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
+                              int64_t *total_units);
+
+/* One persistent launch over every pair of a described batch.
+ *   descs_dev    device copy of the descriptors from iqa_batch_describe.
+ *   count, total_units  as given to / returned by iqa_batch_describe.
+ *   waves        persistent waves (multiple of 4; 2048 = 8 per CU is a good
+ *                start): wave g processes units g, g+waves, g+2*waves, ...
+ * Allocates nothing and calls nothing but the launch, so it can be captured
+ * into a HIP graph.  The descriptor contents are not validated on the device:
+ * pass exactly what iqa_batch_describe wrote. */
+iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
+                             int64_t waves, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */

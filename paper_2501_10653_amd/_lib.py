@@ -35,6 +35,20 @@ class LaunchCfg(ctypes.Structure):
         return cls(**{k: int(d[k]) for k, _ in cls._fields_})
 
 
+class IqaPair(ctypes.Structure):
+    """Mirror of ``iqa_pair``."""
+
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("NT", ctypes.c_int64), ("D", ctypes.c_float), ("C1", ctypes.c_float),
+                ("C2", ctypes.c_float), ("C", ctypes.c_float), ("lisi", ctypes.c_void_p),
+                ("auglisi", ctypes.c_void_p), ("sums", ctypes.c_void_p)]
+
+
+BATCH_DESC_BYTES = 128
+TUNE_SINGLE = 0
+TUNE_BATCH = 1
+
+
 class IqaError(RuntimeError):
     def __init__(self, status: int, where: str, hip_error: int = 0):
         self.status = status
@@ -77,6 +91,12 @@ def load() -> ctypes.CDLL:
         "iqa_tiles_cfg": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp], ctypes.c_int),
         "iqa_prepare": ([i64, i64, cfgp, vp], ctypes.c_int),
         "iqa_read_ceiling": ([vp, i64, vp, i64, vp], ctypes.c_int),
+        "iqa_tune_set": ([i64, i64, ctypes.c_int, cfgp], ctypes.c_int),
+        "iqa_tune_clear": ([], None),
+        "iqa_batch_cfg": ([i64, i64, cfgp], ctypes.c_int),
+        "iqa_batch_describe": ([ctypes.POINTER(IqaPair), i64, vp, ctypes.POINTER(i64)],
+                               ctypes.c_int),
+        "iqa_tiles_batched": ([vp, i64, i64, i64, vp], ctypes.c_int),
         "iqa_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "iqa_last_hip_error": ([], ctypes.c_int),
         "iqa_version": ([], ctypes.c_int),

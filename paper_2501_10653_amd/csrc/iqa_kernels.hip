@@ -38,6 +38,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "iqa.h"
@@ -152,9 +153,29 @@ template <> struct VecT<4> { using T = float4; };
 template <> struct VecT<2> { using T = float2; };
 template <> struct VecT<1> { using T = float; };
 
+// Streaming loads: every input byte is read exactly once, so they carry the
+// nontemporal hint and do not displace other data in the caches.
 template <int VEC>
 __device__ __forceinline__ typename VecT<VEC>::T vload(const float *p) {
-    return *reinterpret_cast<const typename VecT<VEC>::T *>(p);
+    if constexpr (VEC == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+        return float4{v.x, v.y, v.z, v.w};
+    } else if constexpr (VEC == 2) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2 *>(p));
+        return float2{v.x, v.y};
+    } else {
+        return __builtin_nontemporal_load(p);
+    }
+}
+
+// Load at a wave-uniform base plus a 32-bit per-lane byte offset, which the
+// hardware adds itself (no 64-bit address arithmetic per load).
+template <int VEC>
+__device__ __forceinline__ typename VecT<VEC>::T vload_off(const float *base, uint32_t byte_off) {
+    return vload<VEC>(reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) +
+                                                      byte_off));
 }
 
 template <int VEC>
@@ -173,14 +194,11 @@ __device__ __forceinline__ float velem(const typename VecT<VEC>::T &v, int e) {
     }
 }
 
-// Fold VEC adjacent pixel pairs into a short plain-FP32 block, then add the
-// block into the compensated accumulators.  A pair of zeros (padding) adds
-// nothing.
+// Per-pixel terms of VEC adjacent pixel pairs, added with plain FP32 (FMA
+// chains) into a short block sum b.  A pair of zeros adds nothing.
 template <int VEC, int MODE>
 __device__ __forceinline__ void accumulate(const typename VecT<VEC>::T &xv,
-                                           const typename VecT<VEC>::T &yv,
-                                           float C1, Acc &acc) {
-    float bA = 0.f, bP = 0.f, bX = 0.f, bY = 0.f;
+                                           const typename VecT<VEC>::T &yv, float C1, Sum4 &b) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
         const float xr = velem<VEC>(xv, e);
@@ -191,18 +209,21 @@ __device__ __forceinline__ void accumulate(const typename VecT<VEC>::T &xv,
         const float d = fabsf(xc - yc);         // |x'-y'|
         if constexpr ((MODE & kLisi) != 0) {
             const float r = __builtin_amdgcn_rcpf(d + C1);
-            bA = (e == 0) ? s * r : __builtin_fmaf(s, r, bA);
+            b.A = __builtin_fmaf(s, r, b.A);
         }
-        if constexpr ((MODE & kAug) != 0) {
-            bP = (e == 0) ? s * d : __builtin_fmaf(s, d, bP);
-        }
-        bX = (e == 0) ? xc : bX + xc;
-        bY = (e == 0) ? yc : bY + yc;
+        if constexpr ((MODE & kAug) != 0) b.P = __builtin_fmaf(s, d, b.P);
+        b.X = b.X + xc;
+        b.Y = b.Y + yc;
     }
-    if constexpr ((MODE & kLisi) != 0) cadd(acc.A, bA);
-    if constexpr ((MODE & kAug) != 0) cadd(acc.P, bP);
-    cadd(acc.X, bX);
-    cadd(acc.Y, bY);
+}
+
+// Add a block sum into the Kahan-compensated lane accumulators.
+template <int MODE>
+__device__ __forceinline__ void add_block(Acc &acc, const Sum4 &b) {
+    if constexpr ((MODE & kLisi) != 0) cadd(acc.A, b.A);
+    if constexpr ((MODE & kAug) != 0) cadd(acc.P, b.P);
+    cadd(acc.X, b.X);
+    cadd(acc.Y, b.Y);
 }
 
 // ---------------------------------------------------------------------------
@@ -272,94 +293,106 @@ __device__ __forceinline__ int xcd_remap(int b, int grid) {
 }
 
 // ---------------------------------------------------------------------------
-// The tile kernel
+// One wave's slice of one tile group
 // ---------------------------------------------------------------------------
 //
-// Grid: one workgroup of WAVES waves per (tile group, split part).  A tile
-// group is the ht = 64/(seg*rp) horizontally adjacent tiles one wave covers.
-// The tile's rows are cut into WAVES*ks contiguous slices of rows_wave rows;
-// wave w of part p takes slice p*WAVES + w.  Inside a wave, lane L works on
-// tile j = L >> log_grp of the group, row phase k = (L >> log_seg) & (rp-1) and
-// column group l = L & (seg-1): rows k, k+rp, k+2rp, ... of its slice.
-template <int VEC, int WAVES, int U, int MODE, bool WIDE>
-__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
+// A tile group is the ht = 64/(seg*rp) horizontally adjacent tiles one wave
+// covers: tiles txg*ht .. txg*ht+ht-1 of tile row ty.  A slice is rows
+// slice*rows_wave .. (slice+1)*rows_wave-1 of those tiles.  Lane L works on
+// tile j = L >> log_grp, row phase k = (L >> log_seg) & (rp-1) and column
+// group l = L & (seg-1): rows k, k+rp, k+2rp, ... of the slice.  Returns the
+// slice's sums of tile j, the same on every lane of the tile's lane group.
+template <int VEC, int U, int MODE, bool WIDE>
+__device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int slice, int lane) {
     using V = typename VecT<VEC>::T;
-
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
     const int seg = 1 << a.log_seg;
     const int rp = 1 << (a.log_grp - a.log_seg);
     const int l = lane & (seg - 1);
     const int k = (lane >> a.log_seg) & (rp - 1);
     const int j = lane >> a.log_grp;
-
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int grp = bid / a.ks;
-    const int part = bid - grp * a.ks;
-    const int ty = grp / a.ngx;
-    const int txg = grp - ty * a.ngx;
     const int tx = txg * a.ht + j;
 
-    const int slice = part * WAVES + wave;
     int M = 0;   // rows of the tile this lane reduces
     if (tx < a.ns && k < a.rows_wave) M = (a.rows_wave - k + rp - 1) / rp;
-    const int64_t row0 = (int64_t)ty * a.NT + (int64_t)slice * a.rows_wave + k;
     const int64_t col0 = (int64_t)tx * a.NT;
-    const int64_t rstep = (int64_t)rp * a.N;
+    // First row of the slice: uniform across the wave, so the image pointers
+    // below live in scalar registers.
+    const int64_t srow = (int64_t)ty * a.NT + (int64_t)slice * a.rows_wave;
 
     Acc acc = acc_zero();
 
     if constexpr (!WIDE) {
-        // One column group per lane (lanes past the tile row idle), rows in
-        // batches of U, the next batch loading while this one is reduced.
+        // One column group per lane (lanes past the tile row idle).  The slice
+        // spans rows_wave * N floats, which the host keeps below 2^30, so byte
+        // offsets from the slice start fit in 32 bits.
         if (l >= a.lpt) M = 0;
-        const float *px = a.x + row0 * a.N + col0 + (int64_t)l * VEC;
-        const float *py = a.y + row0 * a.N + col0 + (int64_t)l * VEC;
-        V ax[U], ay[U], bx[U], by[U];
+        const float *bx = a.x + srow * a.N;
+        const float *by = a.y + srow * a.N;
+        uint32_t off = (uint32_t)(((int64_t)k * a.N + col0 + (int64_t)l * VEC) * 4);
+        const uint32_t step = (uint32_t)((int64_t)rp * a.N * 4);
+        // Full batches of U rows, double-buffered: the next batch is in flight
+        // while this one is reduced.  Compensation is per batch.
+        int m = 0;
+        if (M >= U) {
+            V ax[U], ay[U], cx[U], cy[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (u < M) {
-                ax[u] = vload<VEC>(px + (int64_t)u * rstep);
-                ay[u] = vload<VEC>(py + (int64_t)u * rstep);
-            } else {
-                ax[u] = vzero<VEC>();
-                ay[u] = vzero<VEC>();
+            for (int u = 0; u < U; ++u) {
+                ax[u] = vload_off<VEC>(bx, off + u * step);
+                ay[u] = vload_off<VEC>(by, off + u * step);
+            }
+            off += U * step;
+            while (true) {
+                const bool more_c = m + 2 * U <= M;
+                if (more_c) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        cx[u] = vload_off<VEC>(bx, off + u * step);
+                        cy[u] = vload_off<VEC>(by, off + u * step);
+                    }
+                    off += U * step;
+                }
+                {
+                    Sum4 b{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(ax[u], ay[u], a.C1, b);
+                    add_block<MODE>(acc, b);
+                }
+                m += U;
+                if (!more_c) break;
+                const bool more_a = m + 2 * U <= M;
+                if (more_a) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        ax[u] = vload_off<VEC>(bx, off + u * step);
+                        ay[u] = vload_off<VEC>(by, off + u * step);
+                    }
+                    off += U * step;
+                }
+                {
+                    Sum4 b{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(cx[u], cy[u], a.C1, b);
+                    add_block<MODE>(acc, b);
+                }
+                m += U;
+                if (!more_a) break;
             }
         }
-        for (int m = 0; m < M; m += 2 * U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = m + U + u;
-                if (r < M) {
-                    bx[u] = vload<VEC>(px + (int64_t)r * rstep);
-                    by[u] = vload<VEC>(py + (int64_t)r * rstep);
-                } else {
-                    bx[u] = vzero<VEC>();
-                    by[u] = vzero<VEC>();
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(ax[u], ay[u], a.C1, acc);
-            if (m + U >= M) break;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r = m + 2 * U + u;
-                if (r < M) {
-                    ax[u] = vload<VEC>(px + (int64_t)r * rstep);
-                    ay[u] = vload<VEC>(py + (int64_t)r * rstep);
-                } else {
-                    ax[u] = vzero<VEC>();
-                    ay[u] = vzero<VEC>();
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(bx[u], by[u], a.C1, acc);
+        // Remaining rows (fewer than U), one at a time.
+        for (; m < M; ++m) {
+            const V xv = vload_off<VEC>(bx, off);
+            const V yv = vload_off<VEC>(by, off);
+            off += step;
+            Sum4 b{0.f, 0.f, 0.f, 0.f};
+            accumulate<VEC, MODE>(xv, yv, a.C1, b);
+            add_block<MODE>(acc, b);
         }
     } else {
         // Tile rows wider than a segment: chunk q covers column group l + q*seg.
         for (int m = 0; m < M; ++m) {
-            const float *px = a.x + (row0 + (int64_t)m * rp) * a.N + col0;
-            const float *py = a.y + (row0 + (int64_t)m * rp) * a.N + col0;
+            const int64_t row = srow + k + (int64_t)m * rp;
+            const float *px = a.x + row * a.N + col0;
+            const float *py = a.y + row * a.N + col0;
             for (int q0 = 0; q0 < a.cpl; q0 += U) {
                 V xv[U], yv[U];
 #pragma unroll
@@ -373,14 +406,38 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
                         yv[u] = vzero<VEC>();
                     }
                 }
+                Sum4 b{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(xv[u], yv[u], a.C1, acc);
+                for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(xv[u], yv[u], a.C1, b);
+                add_block<MODE>(acc, b);
             }
         }
     }
 
     // Sum the lanes of each tile inside the wave.
-    const Sum4 s = group_allreduce<MODE>(fold(acc), a.log_grp);
+    return group_allreduce<MODE>(fold(acc), a.log_grp);
+}
+
+// ---------------------------------------------------------------------------
+// The tile kernel (one image pair)
+// ---------------------------------------------------------------------------
+//
+// Grid: one workgroup of WAVES waves per (tile group, split part).  The tile
+// rows are cut into WAVES*ks contiguous slices of rows_wave rows; wave w of
+// part p takes slice p*WAVES + w.
+template <int VEC, int WAVES, int U, int MODE, bool WIDE>
+__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int grp = bid / a.ks;
+    const int part = bid - grp * a.ks;
+    const int ty = grp / a.ngx;
+    const int txg = grp - ty * a.ngx;
+    const int j = lane >> a.log_grp;
+    const int tx = txg * a.ht + j;
+
+    const Sum4 s = slice_sums<VEC, U, MODE, WIDE>(a, ty, txg, part * WAVES + wave, lane);
     const bool leader = (lane & ((1 << a.log_grp) - 1)) == 0;
 
     if constexpr (WAVES == 1) {
@@ -399,21 +456,70 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
         if (wave != 0 || lane >= a.ht) return;
         const int txl = txg * a.ht + lane;
         if (txl >= a.ns) return;
-        Acc c = acc_zero();
+        // Pairwise tree over the waves' partials (all non-negative).
+        float4 v[WAVES];
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            const float4 v = lds[w][lane];
-            if constexpr ((MODE & kLisi) != 0) cadd(c.A, v.x);
-            if constexpr ((MODE & kAug) != 0) cadd(c.P, v.y);
-            cadd(c.X, v.z);
-            cadd(c.Y, v.w);
+        for (int w = 0; w < WAVES; ++w) v[w] = lds[w][lane];
+#pragma unroll
+        for (int h = 1; h < WAVES; h *= 2) {
+#pragma unroll
+            for (int w = 0; w + h < WAVES; w += 2 * h) {
+                v[w].x += v[w + h].x;
+                v[w].y += v[w + h].y;
+                v[w].z += v[w + h].z;
+                v[w].w += v[w + h].w;
+            }
         }
         if (a.ks == 1) {
-            finalize<MODE>(a, (int64_t)ty * a.ns + txl, c);
+            finalize<MODE>(a, (int64_t)ty * a.ns + txl, acc_of(Sum4{v[0].x, v[0].y, v[0].z, v[0].w}));
         } else {
-            float4 v{c.A.hi + c.A.lo, c.P.hi + c.P.lo, c.X.hi + c.X.lo, c.Y.hi + c.Y.lo};
-            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + lane] = v;
+            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + lane] = v[0];
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The batched kernel (many image pairs of mixed N and N_T, one launch)
+// ---------------------------------------------------------------------------
+//
+// Each pair is described by its own geometry (one wave per tile group, no row
+// split) and by the index of its first work unit; a unit is one tile group of
+// one pair.  A persistent grid of independent waves takes units round-robin:
+// wave g does units g, g + W, g + 2W, ... where W is the number of waves.  A
+// pair's results are bitwise equal to a single-pair launch with the same
+// geometry and unroll (waves = 1, ksplit = 1).
+struct BatchDesc {
+    KArgs a;
+    int64_t unit_begin;
+};
+static_assert(sizeof(BatchDesc) <= IQA_BATCH_DESC_BYTES, "batch descriptor size");
+
+constexpr int kBatchWaves = 4;   // independent waves per workgroup
+
+template <int U>
+__global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel(const BatchDesc *descs,
+                                                                    int count, int64_t units) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int64_t nw = (int64_t)gridDim.x * kBatchWaves;
+    const int64_t g0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBatchWaves + wave;
+    for (int64_t u = g0; u < units; u += nw) {
+        // Binary search for the pair whose units contain u.
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (descs[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+        }
+        const int pi = __builtin_amdgcn_readfirstlane(lo);
+        const KArgs a = descs[pi].a;
+        const int grp = (int)(u - descs[pi].unit_begin);
+        const int ty = grp / a.ngx;
+        const int txg = grp - ty * a.ngx;
+        const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, 0, lane)
+                                 : slice_sums<4, U, kBoth, false>(a, ty, txg, 0, lane);
+        const int tx = txg * a.ht + (lane >> a.log_grp);
+        if ((lane & ((1 << a.log_grp) - 1)) == 0 && tx < a.ns)
+            finalize<kBoth>(a, (int64_t)ty * a.ns + tx, acc_of(s));
     }
 }
 
@@ -509,8 +615,9 @@ LaunchFn pick_unroll(int unroll, int mode, bool wide) {
     }
 }
 
-// The instantiated launch shapes: waves 1/2/4/8 with unroll 4/8 for vec 4,
-// and waves 1/4 with unroll 4 for the narrow vec 2 and vec 1 paths.
+// The instantiated launch shapes: waves 1/2/4/8 with unroll 4/8 and waves 16
+// with unroll 4 for vec 4, and waves 1/4 with unroll 4 for the narrow vec 2
+// and vec 1 paths.
 LaunchFn pick(const iqa_launch_cfg &c, int mode, bool wide) {
     if (c.vec == 4) {
         switch (c.waves) {
@@ -518,6 +625,7 @@ LaunchFn pick(const iqa_launch_cfg &c, int mode, bool wide) {
             case 2: return pick_unroll<4, 2>(c.unroll, mode, wide);
             case 4: return pick_unroll<4, 4>(c.unroll, mode, wide);
             case 8: return pick_unroll<4, 8>(c.unroll, mode, wide);
+            case 16: return c.unroll == 4 ? pick_wide<4, 16, 4>(mode, wide) : nullptr;
             default: return nullptr;
         }
     }
@@ -570,7 +678,7 @@ struct Geometry {
 iqa_status geometry(int64_t N, int64_t NT, const iqa_launch_cfg &c, Geometry &g) {
     if (!(c.vec == 1 || c.vec == 2 || c.vec == 4) || NT % c.vec) return IQA_ERR_CONFIG;
     if (!is_pow2(c.seg) || !is_pow2(c.rp) || (int64_t)c.seg * c.rp > kWave) return IQA_ERR_CONFIG;
-    if (!is_pow2(c.waves) || c.waves > 8) return IQA_ERR_CONFIG;
+    if (!is_pow2(c.waves) || c.waves > 16) return IQA_ERR_CONFIG;
     if (c.ksplit < 1 || NT % ((int64_t)c.waves * c.ksplit) != 0) return IQA_ERR_CONFIG;
     if (pick(c, kBoth, false) == nullptr) return IQA_ERR_CONFIG;
     g.ns = N / NT;
@@ -625,6 +733,46 @@ iqa_launch_cfg default_cfg(int64_t N, int64_t NT, const float *x, const float *y
     return c;
 }
 
+// Tuned launch shapes registered at run time (e.g. by the autotuner's cache):
+// kind 0 = single-pair launches, kind 1 = per-pair geometry in batches.
+std::mutex g_tune_mutex;
+std::map<std::tuple<int64_t, int64_t, int>, iqa_launch_cfg> g_tuned;
+
+bool tuned_lookup(int64_t N, int64_t NT, int kind, iqa_launch_cfg *out) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tuned.find(std::make_tuple(N, NT, kind));
+    if (it == g_tuned.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+iqa_launch_cfg pick_cfg(int64_t N, int64_t NT, const float *x, const float *y) {
+    iqa_launch_cfg c;
+    if (aligned(x, 16) && aligned(y, 16) && tuned_lookup(N, NT, 0, &c)) return c;
+    return default_cfg(N, NT, x, y);
+}
+
+// Per-pair geometry inside a batch: vec 4, one wave per tile group, no row
+// split, and as many tiles per wave as make a unit of about 64 KiB of input.
+constexpr int kBatchUnroll = 8;
+
+iqa_launch_cfg batch_cfg(int64_t N, int64_t NT) {
+    iqa_launch_cfg c;
+    if (tuned_lookup(N, NT, 1, &c)) return c;
+    c.vec = 4;
+    c.waves = 1;
+    c.unroll = kBatchUnroll;
+    c.ksplit = 1;
+    const int64_t lpt = NT / 4;
+    c.seg = (int)std::min<int64_t>(kWave, next_pow2(lpt));
+    const int64_t tpw = kWave / c.seg;
+    const int64_t want = std::max<int64_t>(1, (int64_t(64) << 10) / (8 * NT * NT));
+    int64_t ht = 1;
+    while (ht * 2 <= tpw && ht * 2 <= want && ht * 2 <= next_pow2(N / NT)) ht *= 2;
+    c.rp = (int)(tpw / ht);
+    return c;
+}
+
 // Per (device, stream) workspace for split partials.  Partials are written by
 // tiles_kernel and read by combine_kernel in the same stream order, so one
 // buffer per stream is enough; concurrent streams get their own.
@@ -673,10 +821,35 @@ iqa_status workspace_for(hipStream_t s, size_t bytes, float **out) {
     return IQA_OK;
 }
 
+void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, float D,
+               float C1, float C2, float C, float *lisi, float *aug, float *sums,
+               const iqa_launch_cfg &c, const Geometry &g) {
+    a.x = x;
+    a.y = y;
+    a.N = N;
+    a.NT = (int32_t)NT;
+    a.ns = (int32_t)g.ns;
+    a.ngx = (int32_t)g.ngx;
+    a.log_seg = ilog2(c.seg);
+    a.log_grp = ilog2((int64_t)c.seg * c.rp);
+    a.ht = (int32_t)g.ht;
+    a.ks = c.ksplit;
+    a.rows_wave = (int32_t)(NT / ((int64_t)c.waves * c.ksplit));
+    a.lpt = g.lpt;
+    a.cpl = g.cpl;
+    a.D = D;
+    a.C1 = C1;
+    a.C2 = C2;
+    a.C = C;
+    a.lisi = lisi;
+    a.aug = aug;
+    a.sums = sums;
+}
+
 iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
                float C2, float C, float *lisi, float *aug, float *sums,
                const iqa_launch_cfg *cfg_in, void *stream, bool prepare_only) {
-    iqa_launch_cfg c = cfg_in ? *cfg_in : default_cfg(N, NT, x, y);
+    iqa_launch_cfg c = cfg_in ? *cfg_in : pick_cfg(N, NT, x, y);
     Geometry g{};
     iqa_status st = geometry(N, NT, c, g);
     if (st != IQA_OK) return st;
@@ -698,26 +871,7 @@ iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, f
     }
     if (prepare_only) return IQA_OK;
 
-    a.x = x;
-    a.y = y;
-    a.N = N;
-    a.NT = (int32_t)NT;
-    a.ns = (int32_t)g.ns;
-    a.ngx = (int32_t)g.ngx;
-    a.log_seg = ilog2(c.seg);
-    a.log_grp = ilog2((int64_t)c.seg * c.rp);
-    a.ht = (int32_t)g.ht;
-    a.ks = c.ksplit;
-    a.rows_wave = (int32_t)(NT / ((int64_t)c.waves * c.ksplit));
-    a.lpt = g.lpt;
-    a.cpl = g.cpl;
-    a.D = D;
-    a.C1 = C1;
-    a.C2 = C2;
-    a.C = C;
-    a.lisi = lisi;
-    a.aug = aug;
-    a.sums = sums;
+    fill_args(a, x, y, N, NT, D, C1, C2, C, lisi, aug, sums, c, g);
     fn(a, (unsigned)g.grid, s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && c.ksplit > 1) {
@@ -739,6 +893,16 @@ iqa_status check_common(const float *x, const float *y, int64_t N, int64_t NT) {
     return IQA_OK;
 }
 
+iqa_status check_outputs_params(float *lisi, float *auglisi, float *sums, float D, float C1,
+                                float C2, float C) {
+    if (!lisi && !auglisi && !sums) return IQA_ERR_NULL;
+    if (!aligned(lisi, 4) || !aligned(auglisi, 4) || !aligned(sums, 16)) return IQA_ERR_ALIGN;
+    const bool need_l = lisi || sums, need_a = auglisi || sums;
+    if (need_l && (!param_ok(D) || !param_ok(C1) || !param_ok(C2))) return IQA_ERR_PARAM;
+    if (need_a && !param_ok(C)) return IQA_ERR_PARAM;
+    return IQA_OK;
+}
+
 }  // namespace iqa
 
 using namespace iqa;
@@ -750,11 +914,8 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT, 
                          const iqa_launch_cfg *cfg, void *stream) {
     iqa_status st = check_common(x, y, N, NT);
     if (st != IQA_OK) return st;
-    if (!lisi && !auglisi && !sums) return IQA_ERR_NULL;
-    if (!aligned(lisi, 4) || !aligned(auglisi, 4) || !aligned(sums, 16)) return IQA_ERR_ALIGN;
-    const bool need_l = lisi || sums, need_a = auglisi || sums;
-    if (need_l && (!param_ok(D) || !param_ok(C1) || !param_ok(C2))) return IQA_ERR_PARAM;
-    if (need_a && !param_ok(C)) return IQA_ERR_PARAM;
+    st = check_outputs_params(lisi, auglisi, sums, D, C1, C2, C);
+    if (st != IQA_OK) return st;
     return run(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, cfg, stream, false);
 }
 
@@ -789,7 +950,7 @@ iqa_status iqa_default_cfg(int64_t N, int64_t NT, const float *x, const float *y
     if (!cfg) return IQA_ERR_NULL;
     iqa_status st = check_shape(N, NT);
     if (st != IQA_OK) return st;
-    *cfg = default_cfg(N, NT, x, y);
+    *cfg = pick_cfg(N, NT, x, y);
     return IQA_OK;
 }
 
@@ -807,6 +968,91 @@ iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *s
     const float *probe = reinterpret_cast<const float *>(uintptr_t(256));
     return run(probe, probe, N, NT, 1.f, 1.f, 1.f, 1.f, nullptr, nullptr, nullptr, cfg, stream,
                true);
+}
+
+iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *cfg) {
+    if (!cfg) return IQA_ERR_NULL;
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    if (kind != IQA_TUNE_SINGLE && kind != IQA_TUNE_BATCH) return IQA_ERR_CONFIG;
+    Geometry g{};
+    st = geometry(N, NT, *cfg, g);
+    if (st != IQA_OK) return st;
+    if (cfg->vec != 4) return IQA_ERR_CONFIG;
+    if (kind == IQA_TUNE_BATCH &&
+        (cfg->waves != 1 || cfg->ksplit != 1 || cfg->unroll != kBatchUnroll))
+        return IQA_ERR_CONFIG;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tuned[std::make_tuple(N, NT, kind)] = *cfg;
+    return IQA_OK;
+}
+
+void iqa_tune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tuned.clear();
+}
+
+iqa_status iqa_batch_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg) {
+    if (!cfg) return IQA_ERR_NULL;
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    if (NT % 4 != 0) return IQA_ERR_CONFIG;
+    *cfg = batch_cfg(N, NT);
+    return IQA_OK;
+}
+
+iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
+                              int64_t *total_units) {
+    if (!pairs || !descs || !total_units) return IQA_ERR_NULL;
+    if (count < 1 || count > INT_MAX) return IQA_ERR_SHAPE;
+    BatchDesc *out = static_cast<BatchDesc *>(descs);
+    int64_t units = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const iqa_pair &p = pairs[i];
+        iqa_status st = check_common(p.x, p.y, p.N, p.NT);
+        if (st != IQA_OK) return st;
+        st = check_outputs_params(p.lisi, p.auglisi, p.sums, p.D, p.C1, p.C2, p.C);
+        if (st != IQA_OK) return st;
+        if (p.NT % 4 != 0) return IQA_ERR_CONFIG;
+        if (!aligned(p.x, 16) || !aligned(p.y, 16)) return IQA_ERR_ALIGN;
+        const iqa_launch_cfg c = batch_cfg(p.N, p.NT);
+        Geometry g{};
+        st = geometry(p.N, p.NT, c, g);
+        if (st != IQA_OK) return st;
+        BatchDesc d;
+        std::memset(&d, 0, sizeof(d));
+        // Outputs a pair does not ask for stay NULL; the batch always computes
+        // all four sums, so lisi and auglisi get the constants they need.
+        fill_args(d.a, p.x, p.y, p.N, p.NT, p.lisi || p.sums ? p.D : 1.f,
+                  p.lisi || p.sums ? p.C1 : 1.f, p.lisi || p.sums ? p.C2 : 1.f,
+                  p.auglisi || p.sums ? p.C : 1.f, p.lisi, p.auglisi, p.sums, c, g);
+        d.unit_begin = units;
+        units += g.groups;
+        std::memcpy(out + i, &d, sizeof(d));
+    }
+    if (units > ((int64_t)1 << 40)) return IQA_ERR_SHAPE;
+    *total_units = units;
+    return IQA_OK;
+}
+
+iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
+                             int64_t waves, void *stream) {
+    if (!descs_dev) return IQA_ERR_NULL;
+    if (count < 1 || count > INT_MAX || total_units < 1) return IQA_ERR_SHAPE;
+    if (!aligned(descs_dev, 16)) return IQA_ERR_ALIGN;
+    if (waves < kBatchWaves || waves % kBatchWaves != 0 || waves / kBatchWaves > INT_MAX)
+        return IQA_ERR_CONFIG;
+    const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
+                                             (total_units + kBatchWaves - 1) / kBatchWaves);
+    hipLaunchKernelGGL(batch_kernel<kBatchUnroll>, dim3((unsigned)blocks),
+                       dim3(kBatchWaves * kWave), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const BatchDesc *>(descs_dev), (int)count, total_units);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return IQA_ERR_HIP;
+    }
+    return IQA_OK;
 }
 
 iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blocks,

@@ -104,7 +104,7 @@ def test_default_cfg_follows_alignment():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(vec=3), dict(vec=4, waves=3), dict(waves=16), dict(seg=12), dict(seg=128), dict(rp=3),
+    dict(vec=3), dict(vec=4, waves=3), dict(waves=16, unroll=8), dict(waves=32), dict(seg=12), dict(seg=128), dict(rp=3),
     dict(seg=16, rp=8), dict(ksplit=0), dict(ksplit=3), dict(vec=2, waves=2),
     dict(vec=1, unroll=8), dict(unroll=16), dict(unroll=2), dict(waves=8, ksplit=16),
 ])
@@ -120,3 +120,59 @@ def test_cfg_call_rejects_invalid_config_before_launch():
     st = _lib.load().iqa_tiles_cfg(FAKE, FAKE, 2048, 64, C6 / 2, C6, C6, C6, FAKE, None, None,
                                    ctypes.byref(bad), None)
     assert st == CONFIG
+
+
+def make_pairs(n, **over):
+    arr = (_lib.IqaPair * n)()
+    for i in range(n):
+        kw = dict(x=FAKE, y=FAKE, N=256, NT=32, D=C6 / 2, C1=C6, C2=C6, C=C6, lisi=FAKE,
+                  auglisi=FAKE, sums=None)
+        kw.update(over)
+        arr[i] = _lib.IqaPair(**kw)
+    return arr
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(), OK), (dict(NT=30, N=300), CONFIG), (dict(x=FAKE + 4), ALIGN), (dict(N=100, NT=8), SHAPE),
+    (dict(C=0.0), PARAM), (dict(lisi=None, auglisi=None), NULL), (dict(y=None), NULL),
+])
+def test_batch_describe_validates_every_pair(over, status):
+    import numpy as np
+    arr = make_pairs(3, **over)
+    buf = np.zeros(3 * _lib.BATCH_DESC_BYTES, np.uint8)
+    units = ctypes.c_int64(-1)
+    st = _lib.load().iqa_batch_describe(arr, 3, buf.ctypes.data, ctypes.byref(units))
+    assert st == status
+    if status == OK:
+        # 256/32: 8x8 tiles, 8 tiles per wave -> 8 units per pair
+        assert units.value == 3 * 8
+
+
+def test_batch_launch_validation():
+    lib = _lib.load()
+    assert lib.iqa_tiles_batched(None, 1, 1, 2048, None) == NULL
+    assert lib.iqa_tiles_batched(FAKE, 0, 1, 2048, None) == SHAPE
+    assert lib.iqa_tiles_batched(FAKE, 1, 0, 2048, None) == SHAPE
+    assert lib.iqa_tiles_batched(FAKE, 1, 1, 2046, None) == CONFIG
+    assert lib.iqa_tiles_batched(FAKE + 8, 1, 1, 2048, None) == ALIGN
+
+
+def test_tune_registry():
+    lib = _lib.load()
+    try:
+        good = LaunchCfg.from_dict(dict(vec=4, waves=1, unroll=8, seg=16, rp=2, ksplit=1))
+        assert lib.iqa_tune_set(2048, 64, _lib.TUNE_SINGLE, ctypes.byref(good)) == OK
+        st, c = default_cfg(2048, 64)
+        assert st == OK and c == good.as_dict()
+        # unaligned images ignore tuned vec-4 entries
+        assert default_cfg(2048, 64, FAKE + 4, FAKE)[1]["vec"] == 1
+        assert lib.iqa_tune_set(2048, 64, _lib.TUNE_BATCH, ctypes.byref(good)) == OK
+        c2 = LaunchCfg()
+        assert lib.iqa_batch_cfg(2048, 64, ctypes.byref(c2)) == OK and c2.as_dict() == good.as_dict()
+        bad = LaunchCfg.from_dict(dict(vec=4, waves=2, unroll=8, seg=16, rp=2, ksplit=1))
+        assert lib.iqa_tune_set(2048, 64, _lib.TUNE_BATCH, ctypes.byref(bad)) == CONFIG
+        assert lib.iqa_tune_set(2048, 64, 7, ctypes.byref(good)) == CONFIG
+        assert lib.iqa_tune_set(2048, 63, 0, ctypes.byref(good)) == SHAPE
+    finally:
+        lib.iqa_tune_clear()
+    assert default_cfg(2048, 64)[1]["rp"] == 4   # built-in choice again

@@ -93,7 +93,7 @@ def all_configs(N, NT):
     """Every instantiated (vec, waves, unroll) with a spread of rp and ksplit."""
     out = []
     combos = [(4, w, u) for w in (1, 2, 4, 8) for u in (4, 8)] + \
-        [(2, 1, 4), (2, 4, 4), (1, 1, 4), (1, 4, 4)]
+        [(4, 16, 4), (2, 1, 4), (2, 4, 4), (1, 1, 4), (1, 4, 4)]
     for vec, waves, unroll in combos:
         if NT % vec:
             continue
