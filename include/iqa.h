@@ -151,6 +151,28 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT,
 iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Hierarchical aggregation (Eq. 3, Eq. 4)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Merge f x f blocks of tiles into larger tiles (Sec. 3: the IQA values of
+ * tiles aggregate exactly into the value of the whole image, or of a larger
+ * tile formed by merging smaller ones; Eq. 3 for LISI, Eq. 4 for augLISI).
+ *   sums_in   device, ns*ns*4 floats: the `sums` output of iqa_tiles (A, P,
+ *             Sx, Sy per tile, row-major tiles), 16-byte aligned.
+ *   ns, f     tiles per side of the input level; f divides ns.  The output
+ *             level has (ns/f)^2 tiles; f == ns gives the whole image.
+ *   D, C2, C  as in iqa_tiles (C1 is already inside A).
+ *   lisi, auglisi, sums_out  device, (ns/f)^2 floats / (ns/f)^2 * 4 floats,
+ *             each nullable, at least one non-NULL.  sums_out feeds the next
+ *             level, so a pyramid N_T, 2N_T, 4N_T, ... is a chain of calls.
+ * Eq. 3/4 weight each child's index by its own denominator, which equals
+ * adding the children's sums and applying Eq. 1/2 to the totals; the kernel
+ * does the latter (Kahan-compensated, fixed order) and so avoids the
+ * cancellation of reconstructing sums from rounded indices. */
+iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D, float C2,
+                           float C, float *lisi, float *auglisi, float *sums_out, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Tuned launch shapes                                                       */
 /* ------------------------------------------------------------------------ */
 

@@ -91,6 +91,7 @@ def load() -> ctypes.CDLL:
         "iqa_tiles_cfg": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp], ctypes.c_int),
         "iqa_prepare": ([i64, i64, cfgp, vp], ctypes.c_int),
         "iqa_read_ceiling": ([vp, i64, vp, i64, vp], ctypes.c_int),
+        "iqa_merge_tiles": ([vp, i64, i64, f, f, f, vp, vp, vp, vp], ctypes.c_int),
         "iqa_tune_set": ([i64, i64, ctypes.c_int, cfgp], ctypes.c_int),
         "iqa_tune_clear": ([], None),
         "iqa_batch_cfg": ([i64, i64, cfgp], ctypes.c_int),

@@ -109,18 +109,28 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Partner value for step `stride` of an all-reduce inside aligned groups of
-// 2*stride lanes.  Strides 1 and 2 swap within quads; 4 and 8 mirror within
-// half-rows / rows, which pairs every lane with the other half of its group
-// once the smaller strides have made each half uniform; 16 and 32 cross rows.
-__device__ __forceinline__ float partner(float v, int stride) {
-    switch (stride) {
-        case 1: return dpp<0xB1>(v);    // quad_perm [1,0,3,2]
-        case 2: return dpp<0x4E>(v);    // quad_perm [2,3,0,1]
-        case 4: return dpp<0x141>(v);   // row_half_mirror
-        case 8: return dpp<0x140>(v);   // row_mirror
-        default: return __shfl_xor(v, stride, kWave);
-    }
+// All-reduce steps inside aligned lane groups.  Within a row of 16 lanes the
+// partner comes from a DPP permutation: quad swaps for strides 1 and 2, then
+// half-row and row mirrors for 4 and 8 (once the smaller strides have made
+// each half uniform, a mirror pairs every lane with the other half).  Across
+// rows, gfx950's permlane swaps exchange whole rows (16) or half-waves (32):
+// with both operands equal, the two results are the two halves, and their sum
+// is the same on every lane.
+template <int CTRL>
+__device__ __forceinline__ void dpp_add(float &v) {
+    v += dpp<CTRL>(v);
+}
+
+__device__ __forceinline__ void swap16_add(float &v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v),
+                                                    false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void swap32_add(float &v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
+                                                    false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Plain sums over aligned groups of 2^log_g lanes; every lane of a group ends
@@ -129,14 +139,22 @@ struct Sum4 {
     float A, P, X, Y;
 };
 
+template <int MODE, typename Step>
+__device__ __forceinline__ void each(Sum4 &s, Step step) {
+    if constexpr ((MODE & kLisi) != 0) step(s.A);
+    if constexpr ((MODE & kAug) != 0) step(s.P);
+    step(s.X);
+    step(s.Y);
+}
+
 template <int MODE>
 __device__ __forceinline__ Sum4 group_allreduce(Sum4 s, int log_g) {
-    for (int st = 1; st < (1 << log_g); st <<= 1) {
-        if constexpr ((MODE & kLisi) != 0) s.A += partner(s.A, st);
-        if constexpr ((MODE & kAug) != 0) s.P += partner(s.P, st);
-        s.X += partner(s.X, st);
-        s.Y += partner(s.Y, st);
-    }
+    if (log_g > 0) each<MODE>(s, [](float &v) { dpp_add<0xB1>(v); });   // quad_perm [1,0,3,2]
+    if (log_g > 1) each<MODE>(s, [](float &v) { dpp_add<0x4E>(v); });   // quad_perm [2,3,0,1]
+    if (log_g > 2) each<MODE>(s, [](float &v) { dpp_add<0x141>(v); });  // row_half_mirror
+    if (log_g > 3) each<MODE>(s, [](float &v) { dpp_add<0x140>(v); });  // row_mirror
+    if (log_g > 4) each<MODE>(s, [](float &v) { swap16_add(v); });
+    if (log_g > 5) each<MODE>(s, [](float &v) { swap32_add(v); });
     return s;
 }
 
@@ -545,6 +563,61 @@ __global__ __launch_bounds__(256) void combine_kernel(KArgs a) {
         cadd(c.Y, v.w);
     }
     finalize<MODE>(a, t, c);
+}
+
+// ---------------------------------------------------------------------------
+// Hierarchical aggregation (Eq. 3, Eq. 4)
+// ---------------------------------------------------------------------------
+//
+// Eq. 3 and Eq. 4 recover the value of a larger tile (or of the whole image)
+// from its child tiles.  Both weight each child's index by its own
+// denominator, which is the same as adding the children's sums A, P, Sx, Sy
+// and applying Eq. 1 / Eq. 2 to the totals; that is what this kernel does,
+// from the sums iqa_tiles exports.  One workgroup per parent tile: each thread
+// adds a fixed stride of children with Kahan compensation, the wave and the
+// workgroup then add in a fixed order, and thread 0 finalises.
+struct MergeArgs {
+    const float *sums_in;   // ns*ns children, 4 floats each
+    int64_t ns;             // children per side
+    int64_t f;              // children per parent side
+    float D, C2, C;
+    float *lisi;
+    float *aug;
+    float *sums;
+};
+
+__global__ __launch_bounds__(256) void merge_kernel(MergeArgs m) {
+    const int64_t np = m.ns / m.f;
+    const int64_t p = blockIdx.x;
+    const int64_t py = p / np, px = p - py * np;
+    const int64_t nchild = m.f * m.f;
+    Acc acc = acc_zero();
+    const float4 *in = reinterpret_cast<const float4 *>(m.sums_in);
+    for (int64_t c = threadIdx.x; c < nchild; c += 256) {
+        const int64_t cy = c / m.f, cx = c - cy * m.f;
+        const float4 v = in[(py * m.f + cy) * m.ns + px * m.f + cx];
+        cadd(acc.A, v.x);
+        cadd(acc.P, v.y);
+        cadd(acc.X, v.z);
+        cadd(acc.Y, v.w);
+    }
+    Sum4 s = group_allreduce<kBoth>(fold(acc), 6);
+    __shared__ float4 part[4];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane == 0) part[wave] = float4{s.A, s.P, s.X, s.Y};
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const float4 a = part[0], b = part[1], c = part[2], d = part[3];
+    const Sum4 t{(a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y),
+                 (a.z + b.z) + (c.z + d.z), (a.w + b.w) + (c.w + d.w)};
+    KArgs k{};
+    k.D = m.D;
+    k.C2 = m.C2;
+    k.C = m.C;
+    k.lisi = m.lisi;
+    k.aug = m.aug;
+    k.sums = m.sums;
+    finalize<kBoth>(k, p, acc_of(t));
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,6 +1120,26 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
     hipLaunchKernelGGL(batch_kernel<kBatchUnroll>, dim3((unsigned)blocks),
                        dim3(kBatchWaves * kWave), 0, static_cast<hipStream_t>(stream),
                        static_cast<const BatchDesc *>(descs_dev), (int)count, total_units);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return IQA_ERR_HIP;
+    }
+    return IQA_OK;
+}
+
+iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D, float C2,
+                           float C, float *lisi, float *auglisi, float *sums_out, void *stream) {
+    if (!sums_in) return IQA_ERR_NULL;
+    if (ns <= 0 || f <= 0 || ns % f != 0 || ns > IQA_MAX_N) return IQA_ERR_SHAPE;
+    iqa_status st = check_outputs_params(lisi, auglisi, sums_out, D, 1.f, C2, C);
+    if (st != IQA_OK) return st;
+    if (!aligned(sums_in, 16)) return IQA_ERR_ALIGN;
+    const int64_t np = ns / f;
+    if (np * np > INT_MAX) return IQA_ERR_SHAPE;
+    MergeArgs m{sums_in, ns, f, D, C2, C, lisi, auglisi, sums_out};
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)(np * np)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), m);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         g_last_hip_error = (int)e;

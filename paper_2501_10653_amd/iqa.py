@@ -164,3 +164,41 @@ def read_ceiling(buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:
         st = _lib.load().iqa_read_ceiling(buf.data_ptr(), buf.numel(), out.data_ptr(),
                                           out.numel(), _stream_handle(buf.device, stream))
     _lib.check(st, "iqa_read_ceiling")
+
+
+def merge_tiles(sums: torch.Tensor, f: int, *, C1: float = C_DEFAULT, C2: float = C_DEFAULT,
+                C: float = C_DEFAULT, D: Optional[float] = None, stream=None) -> TileResult:
+    """Eq. (3)/(4): merge f x f blocks of tiles (given by their (n, 4) sums
+    from ``iqa_tiles(..., sums=True)``) into larger tiles."""
+    if sums.dtype != torch.float32 or sums.dim() != 2 or sums.shape[1] != 4 or \
+            not sums.is_contiguous():
+        raise ValueError("sums must be a contiguous (n, 4) float32 tensor")
+    ns = int(round(sums.shape[0] ** 0.5))
+    if ns * ns != sums.shape[0]:
+        raise ValueError("sums must hold a square number of tiles")
+    if D is None:
+        D = default_D(C1)
+    npar = ns // f if f > 0 and ns % f == 0 else 0
+    dev = sums.device
+    lo = torch.empty(npar, npar, device=dev)
+    ao = torch.empty(npar, npar, device=dev)
+    so = torch.empty(npar * npar, 4, device=dev)
+    with torch.cuda.device(dev):
+        st = _lib.load().iqa_merge_tiles(sums.data_ptr(), ns, f, D, C2, C, lo.data_ptr(),
+                                         ao.data_ptr(), so.data_ptr(), _stream_handle(dev, stream))
+    _lib.check(st, "iqa_merge_tiles")
+    return TileResult(lo, ao, so)
+
+
+def pyramid(x: torch.Tensor, y: torch.Tensor, NT: int, *, C1: float = C_DEFAULT,
+            C2: float = C_DEFAULT, C: float = C_DEFAULT, D: Optional[float] = None,
+            stream=None) -> list:
+    """Multi-scale IQA matrices: tiles of NT, 2NT, 4NT, ... up to the largest
+    power-of-two multiple of NT that divides N (the whole image when N/NT is a
+    power of two).  One fused pass over the images, then a chain of merges."""
+    levels = [iqa_tiles(x, y, NT, C1=C1, C2=C2, C=C, D=D, sums=True, stream=stream)]
+    ns = x.shape[0] // NT
+    while ns % 2 == 0:
+        levels.append(merge_tiles(levels[-1].sums, 2, C1=C1, C2=C2, C=C, D=D, stream=stream))
+        ns //= 2
+    return levels

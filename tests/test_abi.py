@@ -176,3 +176,16 @@ def test_tune_registry():
     finally:
         lib.iqa_tune_clear()
     assert default_cfg(2048, 64)[1]["rp"] == 4   # built-in choice again
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(sums_in=None), NULL), (dict(ns=8, f=3), SHAPE), (dict(f=0), SHAPE), (dict(ns=0), SHAPE),
+    (dict(lisi=None, aug=None, out=None), NULL), (dict(sums_in=FAKE + 4), ALIGN),
+    (dict(C=0.0), PARAM), (dict(D=float("nan")), PARAM),
+])
+def test_merge_validation(args, status):
+    kw = dict(sums_in=FAKE, ns=8, f=2, D=C6 / 2, C2=C6, C=C6, lisi=FAKE, aug=FAKE, out=None)
+    kw.update(args)
+    st = _lib.load().iqa_merge_tiles(kw["sums_in"], kw["ns"], kw["f"], kw["D"], kw["C2"], kw["C"],
+                                     kw["lisi"], kw["aug"], kw["out"], None)
+    assert st == status
