@@ -41,7 +41,8 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="paper",
-                    help="paper (2048/64, default), small (256/32) or N:NT (sweep recipe)")
+                    help="paper (2048/64, default), small (256/32), N:NT (sweep recipe) "
+                         "or serve (request-rate sweep)")
     ap.add_argument("--pool-bytes", type=float, default=1.0 * 2 ** 30,
                     help="total bytes of distinct pair copies the steps rotate over")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -52,6 +53,11 @@ def parse_args(argv=None):
                     help="also time the read ceiling and the two separate kernels")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: a few eager launches plus a 256 MiB copy of known size")
+    ap.add_argument("--serve-rate", type=float, default=10000.0,
+                    help="Poisson request rate of the serving leg of the default run (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--rates", default="2000,5000,10000,20000,50000",
+                    help="request rates of --workload serve")
     return ap.parse_args(argv)
 
 
@@ -70,15 +76,16 @@ def source_digest() -> str:
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def traffic_record(N: int, NT: int):
+def traffic_record(N: int, NT: int, cfg: dict):
     """HBM bytes per launch from committed rocprofv3 counter runs, valid only
-    while the kernel source is the one the counters were taken on."""
+    while the kernel source and launch shape are the ones the counters were
+    taken on."""
     path = os.path.join(PROFILES, f"traffic_iqa_tiles_{N}_nt{NT}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha256") != source_digest():
+    if rec.get("source_sha256") != source_digest() or rec.get("launch_cfg") != cfg:
         return None
     return rec
 
@@ -121,12 +128,138 @@ def cpu_baseline(x, y, NT, seconds: float, bytes_pair: int, n_tiles: int,
     }
 
 
+class ServingWorld:
+    """Serving workload: 16 resident references with N round-robin over
+    1024/2048/4096, a pool of device-resident snapshots per reference (the
+    faintest sources gone, fresh noise), requests picking a reference
+    uniformly and N_T uniformly from {32, 64}."""
+
+    def __init__(self, torch, dev, snapshots_per_ref: int = 2, seed: int = 11):
+        from paper_2501_10653_amd import synth
+        self.torch = torch
+        self.specs = synth.serving_references(count=16, seed=seed)
+        self.refs, self.snaps = [], []
+        for sp in self.specs:
+            x, _, _ = synth.make_pair(sp)
+            self.refs.append(torch.from_numpy(x).to(dev))
+            self.snaps.append([torch.from_numpy(synth.make_snapshot(sp, k)).to(dev)
+                               for k in range(snapshots_per_ref)])
+
+    def requests(self, srv, ids, count: int, seed: int):
+        rng = np.random.default_rng((seed, 3))
+        out, nbytes = [], 0
+        for i in range(count):
+            r = int(rng.integers(len(self.refs)))
+            k = int(rng.integers(len(self.snaps[r])))
+            NT = int(rng.choice([32, 64]))
+            out.append(srv.request(self.snaps[r][k], ids[r], NT))
+            nbytes += 8 * self.specs[r].N ** 2
+        return out, nbytes
+
+
+def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 30,
+                streams: int = 2, max_batch: int = 512, seed: int = 0) -> dict:
+    from paper_2501_10653_amd import synth
+    from paper_2501_10653_amd.serve import Server, latency_summary
+    count = max(200, int(rate * seconds))
+    with Server(budget, streams=streams, max_batch=max_batch) as srv:
+        ids = [srv.add_reference(r) for r in world.refs]
+        reqs, nbytes = world.requests(srv, ids, count, seed)
+        arrivals = synth.poisson_arrivals(rate, count, seed=seed)
+        comps = srv.replay(reqs, arrivals, timeout_s=120.0)
+        st = srv.stats()
+    summ = latency_summary(comps)
+    summ.update({"offered_rps": rate, "requests": count, "batches": st["batches"],
+                 "max_batch": st["max_batch"],
+                 "peak_in_flight_MiB": round(st["peak_in_flight_bytes"] / 2 ** 20, 1),
+                 "budget_GiB": budget / 2 ** 30, "streams": streams,
+                 "GBs_delivered": round(nbytes * summ.get("throughput_rps", 0) / count / 1e9, 1)})
+    for k in ("p50_us", "p99_us", "max_us", "mean_us", "throughput_rps", "span_s"):
+        if k in summ:
+            summ[k] = round(summ[k], 2)
+    return summ
+
+
+def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
+    """Ragged batch: `count` pairs with N uniform over {512, 1024, 2048, 4096}
+    and N_T over {32, 64, 128}, 20% with 1-5 faintest sources removed and the
+    rest noise-only.  One prototype pair is generated per (N, kind) and copied
+    into distinct device buffers for every pair (timing is content-independent).
+    Times one persistent launch (eager and graph-replayed) against `count`
+    single-pair launches (eager and graph-replayed)."""
+    from paper_2501_10653_amd import iqa_tiles, synth
+    from paper_2501_10653_amd.batch import Batch
+    specs = synth.ragged_specs(count=count, seed=seed)
+    proto = {}
+    for N in sorted({sp.N for sp in specs}):
+        for kind in (0, 1):
+            sp = synth.PairSpec(N=N, NT=64, n_src=synth.scaled_count(33, N, 1), amp_lo=1e-3,
+                                amp_hi=2.0, fwhm=4.0, noise_sigma=1e-4,
+                                n_drop=3 if kind else 0, seed=N * 10 + kind)
+            x, y, _ = synth.make_pair(sp)
+            proto[(N, kind)] = (torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev))
+    pairs = []
+    for sp in specs:
+        x, y = proto[(sp.N, 1 if sp.n_drop else 0)]
+        pairs.append((x.clone(), y.clone(), sp.NT))
+    del proto
+    total = sum(8 * p[0].shape[0] ** 2 for p in pairs)
+    s = torch.cuda.Stream(dev)
+
+    def timeit(fn, reps=5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0.record(s)
+            fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    b = Batch(pairs)
+    out = {"pairs": count, "bytes": total, "units": b.units, "waves": b.waves}
+    ms = timeit(lambda: b.run(stream=s))
+    out["batched_eager_ms"] = round(ms, 4)
+    g = b.capture(s)
+
+    def replay(graph):
+        with torch.cuda.stream(s):
+            graph.replay()
+
+    ms = timeit(lambda: replay(g))
+    out["batched_graph_ms"] = round(ms, 4)
+    out["batched_graph_GBs"] = round(total / ms / 1e6, 1)
+    outs = [(torch.empty(p[0].shape[0] // p[2], p[0].shape[0] // p[2], device=dev),
+             torch.empty(p[0].shape[0] // p[2], p[0].shape[0] // p[2], device=dev))
+            for p in pairs]
+
+    def plain():
+        for (x, y, NT), (lo, ao) in zip(pairs, outs):
+            iqa_tiles(x, y, NT, out={"lisi": lo, "auglisi": ao}, stream=s)
+
+    ms = timeit(plain)
+    out["plain_eager_ms"] = round(ms, 4)
+    out["plain_eager_GBs"] = round(total / ms / 1e6, 1)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        plain()
+    ms = timeit(lambda: replay(g2))
+    out["plain_graph_ms"] = round(ms, 4)
+    out["plain_graph_GBs"] = round(total / ms / 1e6, 1)
+    out["hbm_frac_batched"] = round(out["batched_graph_GBs"] / HBM_PEAK_GBS, 4)
+    return out
+
+
 def main(argv=None) -> int:
     args = parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "single-GPU path: run with --gpus 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md but not built)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU (--gpus 1); the path "
+                                   "is single-GPU and no multi-GPU launch is provided"}))
         return 2
 
     import torch
@@ -138,6 +271,30 @@ def main(argv=None) -> int:
         return 1
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.workload == "ragged":
+        r = run_ragged(torch, dev)
+        print(json.dumps({"metric": "ragged batch HBM GB/s (one persistent launch, graph)",
+                          "value": r["batched_graph_GBs"], "unit": "GB/s",
+                          "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+                          "data": "synthetic",
+                          "config": {"workload": "256 FP32 pairs, N in {512..4096}, "
+                                                 "N_T in {32, 64, 128}"},
+                          "detail": r}), flush=True)
+        return 0
+
+    if args.workload == "serve":
+        world = ServingWorld(torch, dev)
+        rows = [run_serving(torch, world, float(r), args.serve_seconds, seed=i)
+                for i, r in enumerate(args.rates.split(","))]
+        print(json.dumps({"metric": "p99 request latency (serving, device-resident snapshots)",
+                          "unit": "us", "higher_is_better": False, "n_gpus": 1,
+                          "data": "synthetic",
+                          "config": {"workload": "16 resident references (N 1024/2048/4096), "
+                                                 "snapshots vs reference, N_T in {32, 64}, "
+                                                 "Poisson arrivals"},
+                          "rates": rows}), flush=True)
+        return 0
 
     spec = workload_spec(args.workload)
     N, NT = spec.N, spec.NT
@@ -220,7 +377,7 @@ def main(argv=None) -> int:
         extras = run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling,
                             lisi_tiles, auglisi_tiles, iqa_tiles, cfg, bytes_pair)
 
-    traffic = traffic_record(N, NT)
+    traffic = traffic_record(N, NT, cfg)
     roofline = {
         "bound": "hbm",
         "achieved": round(gbs, 1),
@@ -255,6 +412,11 @@ def main(argv=None) -> int:
     }
     if extras:
         line["extras"] = extras
+    if args.serve_rate > 0 and args.workload == "paper":
+        del xs, ys
+        torch.cuda.empty_cache()
+        world = ServingWorld(torch, dev)
+        line["serving"] = run_serving(torch, world, args.serve_rate, args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, NT, args.cpu_seconds, bytes_pair, ns * ns,
                                             gpu_lisi, gpu_aug)

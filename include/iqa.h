@@ -70,7 +70,9 @@ typedef enum iqa_status {
     IQA_ERR_HIP = 5,     /* a HIP runtime call or kernel launch failed */
     IQA_ERR_CONFIG = 6,  /* a launch configuration is invalid for the shape, or the
                             shape needs more than 2^31-1 workgroups */
-    IQA_ERR_CAPTURE = 7  /* workspace would have to grow while the stream is captured */
+    IQA_ERR_CAPTURE = 7, /* workspace would have to grow while the stream is captured */
+    IQA_ERR_BUDGET = 8,  /* a request can never fit the server's HBM budget or arena */
+    IQA_ERR_TIMEOUT = 9  /* a server wait ran out of time */
 } iqa_status;
 
 /* Largest supported image side: 2^17 pixels (64 GiB per FP32 image). */
@@ -179,15 +181,22 @@ iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D,
 #define IQA_TUNE_SINGLE 0   /* shape used by iqa_tiles & co. for (N, NT) */
 #define IQA_TUNE_BATCH 1    /* per-pair geometry inside iqa_tiles_batched */
 
-/* Register a measured-best launch configuration for (N, NT), replacing the
- * built-in choice.  Single-pair entries are used when both images are
- * 16-byte aligned; batch entries must have vec 4, waves 1, ksplit 1 and
- * unroll 8.  IQA_ERR_CONFIG if cfg is invalid for the shape.  Thread-safe;
- * takes effect for calls made after it returns. */
+/* The library's default shapes come from autotuner measurements on gfx950
+ * compiled into it, falling back to a heuristic for shapes it has not seen.
+ * iqa_tune_set registers a configuration for (N, NT) that takes precedence
+ * over both (N == 0: for every N with this NT).  Single-pair entries are used
+ * when both images are 16-byte aligned; batch entries must have vec 4,
+ * waves 1, ksplit 1 and unroll 8.  IQA_ERR_CONFIG if cfg is invalid for the
+ * shape.  Thread-safe; takes effect for calls made after it returns. */
 iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *cfg);
 
-/* Forget every registered configuration. */
+/* Forget every configuration registered with iqa_tune_set (the compiled-in
+ * measurements stay). */
 void iqa_tune_clear(void);
+
+/* Persistent wave count the autotuner found best for iqa_tiles_batched on
+ * this GPU (2048 when no measurement is compiled in). */
+int64_t iqa_batch_default_waves(void);
 
 /* ------------------------------------------------------------------------ */
 /* Ragged batches: many image pairs of mixed N and N_T in one launch         */
@@ -235,6 +244,98 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
  * pass exactly what iqa_batch_describe wrote. */
 iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
                              int64_t waves, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of snapshot-vs-reference requests            */
+/* ------------------------------------------------------------------------ */
+
+/* A server keeps reference images resident on the device and answers
+ * requests "compare this snapshot with reference r at tile size NT".  A
+ * scheduler thread admits requests in arrival order while the bytes held by
+ * admitted, unfinished requests stay within `hbm_budget_bytes` (a request
+ * holds its snapshot, 4*N*N bytes, plus its output matrices), and packs all
+ * admitted requests into one iqa_tiles_batched launch whenever one of
+ * `streams` launch slots is free; a slot frees when its batch's completion
+ * event fires.  Requests arriving while batches run join the next launch, so
+ * batches overlap on the device.  A request's results are bitwise the same
+ * whatever it is batched with (they equal iqa_tiles_cfg with the batch
+ * geometry of iqa_batch_cfg).  All entry points are thread-safe. */
+typedef struct iqa_server iqa_server;
+
+typedef struct iqa_server_opts {
+    int64_t hbm_budget_bytes;  /* admission cap, > 0 */
+    int64_t host_arena_bytes;  /* per slot: device room for snapshots copied from
+                                  host memory (0: device snapshots only) */
+    int64_t waves;             /* persistent waves per launch; 0 = tuned default */
+    int32_t streams;           /* launch slots = batches in flight, 1..16 */
+    int32_t max_batch;         /* requests per launch, 1..2^20 */
+    float D, C1, C2, C;        /* Eq. 1 / Eq. 2 constants for every request */
+} iqa_server_opts;
+
+typedef struct iqa_request {
+    const float *snapshot_dev;   /* device N x N snapshot (16-byte aligned), or NULL */
+    const float *snapshot_host;  /* pinned host snapshot, or NULL; exactly one is set */
+    float *lisi;                 /* device outputs as in iqa_tiles (at least one), */
+    float *auglisi;              /* owned by the caller, untouched until the request */
+    float *sums;                 /* completes */
+    int64_t NT;                  /* tile side: divides the reference's N, NT % 4 == 0 */
+    int32_t ref_id;              /* from iqa_server_add_reference */
+    int32_t reserved;
+    uint64_t tag;                /* returned in the completion */
+} iqa_request;
+
+typedef struct iqa_completion {
+    uint64_t tag;
+    int32_t status;              /* IQA_OK, or why the request was rejected / failed */
+    int32_t reserved;
+    int64_t t_submit_ns;         /* steady-clock times: submitted, admitted, */
+    int64_t t_admit_ns;          /* launched, and seen complete by the scheduler */
+    int64_t t_launch_ns;
+    int64_t t_done_ns;
+} iqa_completion;
+
+typedef struct iqa_server_stats {
+    int64_t submitted, completed, rejected, batches, max_batch;
+    int64_t in_flight_bytes, peak_in_flight_bytes;
+    int32_t last_hip_error;
+    int32_t reserved;
+} iqa_server_stats;
+
+/* Start a server (and its scheduler thread) on the current device.  Returns
+ * IQA_ERR_CONFIG for out-of-range options, IQA_ERR_HIP if a stream, event or
+ * buffer cannot be created. */
+iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out);
+
+/* Register a resident reference (device, N x N, 16-byte aligned, owned by the
+ * caller and kept alive until iqa_server_destroy).  Only before the first
+ * submit. */
+iqa_status iqa_server_add_reference(iqa_server *sv, const float *ref, int64_t N,
+                                    int32_t *ref_id);
+
+/* Queue `count` requests.  Invalid requests, and requests that could never
+ * fit the budget (IQA_ERR_BUDGET), complete at once with that status. */
+iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t count);
+
+/* Move up to `max` completions to `out` (host); returns how many.  Never
+ * blocks. */
+int64_t iqa_server_poll(iqa_server *sv, iqa_completion *out, int64_t max);
+
+/* Wait until every submitted request has completed (IQA_ERR_TIMEOUT after
+ * timeout_ms). */
+iqa_status iqa_server_drain(iqa_server *sv, int64_t timeout_ms);
+
+iqa_status iqa_server_get_stats(iqa_server *sv, iqa_server_stats *stats);
+
+/* Open-loop trace replay, for measurement: a separate thread submits
+ * reqs[i] at start + arrival_ns[i] (non-decreasing), whatever the state of
+ * the server, while this call collects the `count` completions into `out`
+ * (completion order; times relative to the start of the trace). */
+iqa_status iqa_server_replay(iqa_server *sv, const iqa_request *reqs,
+                             const int64_t *arrival_ns, int64_t count, iqa_completion *out,
+                             int64_t timeout_ms);
+
+/* Finish every queued request, stop the scheduler, free the server. */
+iqa_status iqa_server_destroy(iqa_server *sv);
 
 /* ------------------------------------------------------------------------ */
 /* Diagnostics                                                               */

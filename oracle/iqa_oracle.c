@@ -17,7 +17,7 @@
  *   Eq. (3), Eq. (4) (Sec. 3): the per-tile values merge exactly into the value
  *   of the whole image or of any larger tile built from whole tiles.
  *
- * Readings where the paper is silent (each one is listed in the design doc):
+ * Readings where the paper is silent, and the choice made here:
  *   - NaN inputs count as negative (blank pixel -> 0); -0 becomes +0.
  *   - images are row-major (column index fastest); tile t = ty*(N/N_T) + tx.
  *   - N must be a multiple of N_T (no partial edge tiles).

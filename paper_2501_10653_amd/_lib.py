@@ -17,6 +17,7 @@ IQA_OK = 0
 STATUS_NAMES = {
     0: "IQA_OK", 1: "IQA_ERR_NULL", 2: "IQA_ERR_SHAPE", 3: "IQA_ERR_ALIGN",
     4: "IQA_ERR_PARAM", 5: "IQA_ERR_HIP", 6: "IQA_ERR_CONFIG", 7: "IQA_ERR_CAPTURE",
+    8: "IQA_ERR_BUDGET", 9: "IQA_ERR_TIMEOUT",
 }
 
 
@@ -42,6 +43,43 @@ class IqaPair(ctypes.Structure):
                 ("NT", ctypes.c_int64), ("D", ctypes.c_float), ("C1", ctypes.c_float),
                 ("C2", ctypes.c_float), ("C", ctypes.c_float), ("lisi", ctypes.c_void_p),
                 ("auglisi", ctypes.c_void_p), ("sums", ctypes.c_void_p)]
+
+
+class ServerOpts(ctypes.Structure):
+    """Mirror of ``iqa_server_opts``."""
+
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("host_arena_bytes", ctypes.c_int64),
+                ("waves", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("D", ctypes.c_float), ("C1", ctypes.c_float),
+                ("C2", ctypes.c_float), ("C", ctypes.c_float)]
+
+
+class Request(ctypes.Structure):
+    """Mirror of ``iqa_request``."""
+
+    _fields_ = [("snapshot_dev", ctypes.c_void_p), ("snapshot_host", ctypes.c_void_p),
+                ("lisi", ctypes.c_void_p), ("auglisi", ctypes.c_void_p),
+                ("sums", ctypes.c_void_p), ("NT", ctypes.c_int64), ("ref_id", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    """Mirror of ``iqa_completion``."""
+
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64),
+                ("t_admit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    """Mirror of ``iqa_server_stats``."""
+
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_batch", ctypes.c_int64), ("in_flight_bytes", ctypes.c_int64),
+                ("peak_in_flight_bytes", ctypes.c_int64), ("last_hip_error", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 BATCH_DESC_BYTES = 128
@@ -94,10 +132,20 @@ def load() -> ctypes.CDLL:
         "iqa_merge_tiles": ([vp, i64, i64, f, f, f, vp, vp, vp, vp], ctypes.c_int),
         "iqa_tune_set": ([i64, i64, ctypes.c_int, cfgp], ctypes.c_int),
         "iqa_tune_clear": ([], None),
+        "iqa_batch_default_waves": ([], ctypes.c_int64),
         "iqa_batch_cfg": ([i64, i64, cfgp], ctypes.c_int),
         "iqa_batch_describe": ([ctypes.POINTER(IqaPair), i64, vp, ctypes.POINTER(i64)],
                                ctypes.c_int),
         "iqa_tiles_batched": ([vp, i64, i64, i64, vp], ctypes.c_int),
+        "iqa_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], ctypes.c_int),
+        "iqa_server_add_reference": ([vp, vp, i64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "iqa_server_submit": ([vp, ctypes.POINTER(Request), i64], ctypes.c_int),
+        "iqa_server_poll": ([vp, ctypes.POINTER(Completion), i64], ctypes.c_int64),
+        "iqa_server_drain": ([vp, i64], ctypes.c_int),
+        "iqa_server_get_stats": ([vp, ctypes.POINTER(ServerStats)], ctypes.c_int),
+        "iqa_server_replay": ([vp, ctypes.POINTER(Request), ctypes.POINTER(i64), i64,
+                               ctypes.POINTER(Completion), i64], ctypes.c_int),
+        "iqa_server_destroy": ([vp], ctypes.c_int),
         "iqa_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "iqa_last_hip_error": ([], ctypes.c_int),
         "iqa_version": ([], ctypes.c_int),

@@ -19,7 +19,11 @@ from . import _lib
 from ._lib import IqaPair, LaunchCfg
 from .iqa import C_DEFAULT, TileResult, _check_images, _stream_handle, default_D
 
-DEFAULT_WAVES = 2048   # 8 persistent waves per CU on 256 CUs
+
+def default_waves() -> int:
+    """Persistent waves per batch launch: the autotuned value compiled into the
+    library (8 per CU on 256 CUs when untuned)."""
+    return int(_lib.load().iqa_batch_default_waves())
 
 
 def batch_cfg(N: int, NT: int) -> dict:
@@ -41,13 +45,13 @@ class Batch:
 
     def __init__(self, pairs: Sequence, *, C1: float = C_DEFAULT, C2: float = C_DEFAULT,
                  C: float = C_DEFAULT, D: Optional[float] = None, sums: bool = False,
-                 waves: int = DEFAULT_WAVES, device: Optional[torch.device] = None):
+                 waves: Optional[int] = None, device: Optional[torch.device] = None):
         if len(pairs) == 0:
             raise ValueError("empty batch")
         if D is None:
             D = default_D(C1)
         self.device = device or pairs[0][0].device
-        self.waves = int(waves)
+        self.waves = int(waves) if waves is not None else default_waves()
         self.inputs = []
         self.results: List[TileResult] = []
         arr = (IqaPair * len(pairs))()

@@ -765,58 +765,83 @@ iqa_status geometry(int64_t N, int64_t NT, const iqa_launch_cfg &c, Geometry &g)
     return IQA_OK;
 }
 
-// Built-in launch shape for (N, NT): widest aligned vector, one segment per
-// tile row (up to a full wave), as many tiles per wave as keep >= kTarget
-// waves in flight, then row splits across waves and workgroups if the tiles
-// are still too few.
-constexpr int64_t kTargetWaves = 2048;   // 8 per CU on 256 CUs
+// Built-in launch shape for (N, NT), for shapes the autotuner has not
+// measured: widest aligned vector, one segment per tile row (up to a full
+// wave), two row phases per wave, enough waves per workgroup that each lane
+// reduces ~16 rows, and row splits across workgroups while the launch has
+// fewer than ~4 waves per CU.  (The measured shapes cluster around this.)
+constexpr int64_t kTargetWaves = 1024;
 
 iqa_launch_cfg default_cfg(int64_t N, int64_t NT, const float *x, const float *y) {
     iqa_launch_cfg c{};
     c.vec = 1;
     if (NT % 2 == 0 && aligned(x, 8) && aligned(y, 8)) c.vec = 2;
     if (NT % 4 == 0 && aligned(x, 16) && aligned(y, 16)) c.vec = 4;
-    c.unroll = c.vec == 4 ? 8 : 4;
     const int64_t lpt = NT / c.vec;
     c.seg = (int)std::min<int64_t>(kWave, next_pow2(lpt));
     const int64_t tpw = kWave / c.seg;     // segments per wave
     const int64_t ns = N / NT;
-    // Tiles per wave (ht = tpw / rp): start wide, narrow while too few waves
-    // and each segment keeps >= 8 rows.
-    int64_t rp = 1;
-    while (rp < tpw) {
-        const int64_t ht = tpw / rp;
-        const int64_t waves = ns * ((ns + ht - 1) / ht);
-        if (waves >= kTargetWaves || NT / (rp * 2) < 8) break;
-        rp *= 2;
-    }
+    const int64_t rp = std::min<int64_t>(2, tpw);
     c.rp = (int)rp;
     const int64_t ht = tpw / rp;
     const int64_t groups = ns * ((ns + ht - 1) / ht);
     int64_t kw = 1;
-    while (kw < 8 && groups * kw < kTargetWaves && NT % (kw * 2) == 0 && NT / (rp * kw * 2) >= 8)
-        kw *= 2;
+    const int64_t kw_max = c.vec == 4 ? 16 : 4;
+    while (kw < kw_max && NT % (kw * 2) == 0 && NT / (rp * kw * 2) >= 16) kw *= 2;
     if (c.vec != 4 && kw > 1) kw = (NT % 4 == 0) ? 4 : 1;
     int64_t ks = 1;
     while (groups * kw * ks < kTargetWaves && NT % (kw * ks * 2) == 0 &&
-           NT / (rp * kw * ks * 2) >= 8)
+           NT / (rp * kw * ks * 2) >= 4)
         ks *= 2;
     c.waves = (int)kw;
+    c.unroll = (c.vec == 4 && kw <= 8) ? 8 : 4;
     c.ksplit = (int)ks;
     return c;
 }
 
-// Tuned launch shapes registered at run time (e.g. by the autotuner's cache):
-// kind 0 = single-pair launches, kind 1 = per-pair geometry in batches.
+// Tuned launch shapes.  The autotuner's measurements on gfx950 are compiled in
+// (tuned_table.inc, generated by the build from the tuner's JSON cache);
+// entries registered at run time take precedence.  kind 0 = single-pair
+// launches, kind 1 = per-pair geometry in batches; N == 0 matches any N.
+struct TunedEntry {
+    int64_t N, NT;
+    int kind;
+    iqa_launch_cfg cfg;
+};
+#if __has_include("tuned_table.inc")
+#include "tuned_table.inc"
+#else
+static const TunedEntry kTuned[] = {{-1, -1, -1, {0, 0, 0, 0, 0, 0}}};
+static const int kTunedCount = 0;
+static const int64_t kTunedBatchWaves = 0;
+#endif
+
 std::mutex g_tune_mutex;
 std::map<std::tuple<int64_t, int64_t, int>, iqa_launch_cfg> g_tuned;
 
 bool tuned_lookup(int64_t N, int64_t NT, int kind, iqa_launch_cfg *out) {
-    std::lock_guard<std::mutex> lock(g_tune_mutex);
-    auto it = g_tuned.find(std::make_tuple(N, NT, kind));
-    if (it == g_tuned.end()) return false;
-    *out = it->second;
-    return true;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        for (int64_t n : {N, int64_t(0)}) {
+            auto it = g_tuned.find(std::make_tuple(n, NT, kind));
+            if (it != g_tuned.end()) {
+                *out = it->second;
+                return true;
+            }
+        }
+    }
+    for (int64_t n : {N, int64_t(0)}) {
+        for (int i = 0; i < kTunedCount; ++i) {
+            const TunedEntry &e = kTuned[i];
+            if (e.N == n && e.NT == NT && e.kind == kind) {
+                Geometry g{};
+                if (geometry(N, NT, e.cfg, g) != IQA_OK) continue;
+                *out = e.cfg;
+                return true;
+            }
+        }
+    }
+    return false;
 }
 
 iqa_launch_cfg pick_cfg(int64_t N, int64_t NT, const float *x, const float *y) {
@@ -1045,11 +1070,12 @@ iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *s
 
 iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *cfg) {
     if (!cfg) return IQA_ERR_NULL;
-    iqa_status st = check_shape(N, NT);
+    // N == 0 registers the entry for every image size with this tile size.
+    iqa_status st = check_shape(N == 0 ? NT : N, NT);
     if (st != IQA_OK) return st;
     if (kind != IQA_TUNE_SINGLE && kind != IQA_TUNE_BATCH) return IQA_ERR_CONFIG;
     Geometry g{};
-    st = geometry(N, NT, *cfg, g);
+    st = geometry(N == 0 ? NT : N, NT, *cfg, g);
     if (st != IQA_OK) return st;
     if (cfg->vec != 4) return IQA_ERR_CONFIG;
     if (kind == IQA_TUNE_BATCH &&
@@ -1063,6 +1089,10 @@ iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *c
 void iqa_tune_clear(void) {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tuned.clear();
+}
+
+int64_t iqa_batch_default_waves(void) {
+    return kTunedBatchWaves > 0 ? kTunedBatchWaves : 2048;
 }
 
 iqa_status iqa_batch_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg) {
@@ -1176,6 +1206,8 @@ const char *iqa_status_str(int status) {
         case IQA_ERR_HIP: return "IQA_ERR_HIP: a HIP call or kernel launch failed";
         case IQA_ERR_CONFIG: return "IQA_ERR_CONFIG: launch configuration invalid for this shape";
         case IQA_ERR_CAPTURE: return "IQA_ERR_CAPTURE: workspace must grow while the stream is captured";
+        case IQA_ERR_BUDGET: return "IQA_ERR_BUDGET: the request can never fit the server's HBM budget";
+        case IQA_ERR_TIMEOUT: return "IQA_ERR_TIMEOUT: the wait ran out of time";
         default: return "unknown iqa_status";
     }
 }

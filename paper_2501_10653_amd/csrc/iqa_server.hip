@@ -1,0 +1,467 @@
+// Continuous-batching server for snapshot-vs-reference IQA requests.
+//
+// Reference images stay resident in device memory.  Each request names a
+// reference, a tile size and a snapshot (already on the device, or in pinned
+// host memory that the server copies in), plus device buffers for its IQA
+// matrices.  A scheduler thread admits requests in arrival order while the
+// bytes held by admitted, unfinished requests stay under an HBM budget, packs
+// everything admitted into one launch of the persistent batched kernel
+// whenever one of its `streams` launch slots is free, and retires a batch when
+// its completion event has fired.  Requests that arrive while batches run are
+// admitted as budget and slots free up and go out with the next launch, so
+// batches overlap on the device (one stream per slot).
+//
+// A request's results do not depend on what it is batched with: each pair in
+// a batch is reduced by its own waves, in a fixed order.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "iqa.h"
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Ref {
+    const float *ptr;
+    int64_t N;
+};
+
+struct Pending {
+    iqa_request req;
+    int64_t t_submit;
+    int64_t t_admit = 0;
+    int64_t cost = 0;
+};
+
+// One launch slot: its stream, event, pinned descriptor staging, device
+// descriptor table and (for host snapshots) a device snapshot arena.
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void *desc_host = nullptr;
+    void *desc_dev = nullptr;
+    float *arena = nullptr;      // device, for snapshots copied from the host
+    int64_t arena_bytes = 0;
+    bool busy = false;
+    int64_t t_launch = 0;
+    int64_t bytes = 0;           // budget held by this batch
+    std::vector<Pending> reqs;
+};
+
+}  // namespace
+
+struct iqa_server {
+    iqa_server_opts opts{};
+    int device = 0;
+    std::vector<Ref> refs;
+    std::vector<Slot> slots;
+
+    std::mutex mu;               // guards intake, done, counters below
+    std::condition_variable cv;  // wakes the scheduler
+    std::condition_variable cv_done;
+    std::deque<Pending> intake;
+    std::deque<iqa_completion> done;
+    int64_t submitted = 0, completed = 0;
+    int64_t in_flight_bytes = 0, peak_in_flight_bytes = 0;
+    int64_t batches = 0, max_batch_seen = 0, rejected = 0;
+    bool stop = false;
+    int last_hip_error = 0;
+
+    std::deque<Pending> pending;  // scheduler-owned: admitted order
+    std::thread worker;
+
+    void run();
+    bool launch(Slot &s, std::vector<Pending> &batch);
+    void retire(Slot &s, int status);
+};
+
+namespace {
+
+int64_t request_cost(const iqa_server &sv, const iqa_request &r) {
+    const int64_t N = sv.refs[r.ref_id].N;
+    const int64_t ns = N / r.NT;
+    // the snapshot the request holds plus its output matrices
+    return 4 * N * N + 8 * ns * ns + (r.sums ? 16 * ns * ns : 0);
+}
+
+}  // namespace
+
+bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
+    std::vector<iqa_pair> pairs(batch.size());
+    int64_t arena_off = 0;
+    bool ok = true;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        const iqa_request &r = batch[i].req;
+        const Ref &ref = refs[r.ref_id];
+        const float *snap = r.snapshot_dev;
+        if (!snap) {
+            // Copy the host snapshot into this slot's arena (16-byte aligned).
+            const int64_t bytes = 4 * ref.N * ref.N;
+            float *dst = reinterpret_cast<float *>(reinterpret_cast<char *>(s.arena) + arena_off);
+            arena_off += (bytes + 255) & ~int64_t(255);
+            hipError_t e = hipMemcpyAsync(dst, r.snapshot_host, bytes, hipMemcpyHostToDevice,
+                                          s.stream);
+            if (e != hipSuccess) {
+                last_hip_error = (int)e;
+                ok = false;
+            }
+            snap = dst;
+        }
+        pairs[i] = iqa_pair{snap, ref.ptr, ref.N, r.NT, opts.D, opts.C1, opts.C2, opts.C,
+                            r.lisi, r.auglisi, r.sums};
+    }
+    int64_t units = 0;
+    if (ok && iqa_batch_describe(pairs.data(), (int64_t)pairs.size(), s.desc_host, &units) != IQA_OK)
+        ok = false;
+    if (ok) {
+        hipError_t e = hipMemcpyAsync(s.desc_dev, s.desc_host,
+                                      pairs.size() * IQA_BATCH_DESC_BYTES,
+                                      hipMemcpyHostToDevice, s.stream);
+        if (e != hipSuccess) {
+            last_hip_error = (int)e;
+            ok = false;
+        }
+    }
+    if (ok && iqa_tiles_batched(s.desc_dev, (int64_t)pairs.size(), units, opts.waves,
+                                s.stream) != IQA_OK) {
+        last_hip_error = iqa_last_hip_error();
+        ok = false;
+    }
+    if (ok) {
+        hipError_t e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) {
+            last_hip_error = (int)e;
+            ok = false;
+        }
+    }
+    s.reqs.swap(batch);
+    s.busy = true;
+    s.t_launch = now_ns();
+    return ok;
+}
+
+void iqa_server::retire(Slot &s, int status) {
+    const int64_t t = now_ns();
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Pending &p : s.reqs) {
+        iqa_completion c{};
+        c.tag = p.req.tag;
+        c.status = status;
+        c.t_submit_ns = p.t_submit;
+        c.t_admit_ns = p.t_admit;
+        c.t_launch_ns = s.t_launch;
+        c.t_done_ns = t;
+        done.push_back(c);
+    }
+    completed += (int64_t)s.reqs.size();
+    in_flight_bytes -= s.bytes;
+    s.reqs.clear();
+    s.bytes = 0;
+    s.busy = false;
+    cv_done.notify_all();
+}
+
+void iqa_server::run() {
+    (void)hipSetDevice(device);
+    const int64_t budget = opts.hbm_budget_bytes;
+    std::vector<Pending> batch;
+    while (true) {
+        bool idle = true;
+        {
+            std::unique_lock<std::mutex> lock(mu);
+            if (stop && intake.empty() && pending.empty()) {
+                bool any_busy = false;
+                for (const Slot &s : slots) any_busy |= s.busy;
+                if (!any_busy) break;
+            }
+            while (!intake.empty()) {
+                pending.push_back(intake.front());
+                intake.pop_front();
+            }
+        }
+        // Retire finished batches.
+        for (Slot &s : slots) {
+            if (!s.busy) continue;
+            const hipError_t q = hipEventQuery(s.done);
+            if (q == hipSuccess) {
+                retire(s, IQA_OK);
+                idle = false;
+            } else if (q != hipErrorNotReady) {
+                last_hip_error = (int)q;
+                retire(s, IQA_ERR_HIP);
+                idle = false;
+            }
+        }
+        // Launch into a free slot everything the budget admits, in order.
+        for (Slot &s : slots) {
+            if (s.busy || pending.empty()) continue;
+            batch.clear();
+            int64_t held, arena_used = 0;
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                held = in_flight_bytes;
+            }
+            int64_t add = 0;
+            while (!pending.empty() && (int64_t)batch.size() < opts.max_batch) {
+                Pending &p = pending.front();
+                const int64_t N = refs[p.req.ref_id].N;
+                const int64_t snap = p.req.snapshot_dev ? 0 : ((4 * N * N + 255) & ~int64_t(255));
+                if (held + add + p.cost > budget) break;
+                if (arena_used + snap > s.arena_bytes) break;
+                add += p.cost;
+                arena_used += snap;
+                p.t_admit = now_ns();
+                batch.push_back(p);
+                pending.pop_front();
+            }
+            if (batch.empty()) break;
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                in_flight_bytes += add;
+                peak_in_flight_bytes = std::max(peak_in_flight_bytes, in_flight_bytes);
+                batches += 1;
+                max_batch_seen = std::max<int64_t>(max_batch_seen, (int64_t)batch.size());
+            }
+            s.bytes = add;
+            if (!launch(s, batch)) {
+                // Let whatever was enqueued finish before the slot is reused.
+                (void)hipStreamSynchronize(s.stream);
+                retire(s, IQA_ERR_HIP);
+            }
+            idle = false;
+        }
+        if (idle) {
+            std::unique_lock<std::mutex> lock(mu);
+            bool any_busy = false;
+            for (const Slot &s : slots) any_busy |= s.busy;
+            if (any_busy) {
+                lock.unlock();
+                std::this_thread::yield();   // poll the events without sleeping
+            } else if (intake.empty() && !stop) {
+                cv.wait_for(lock, std::chrono::milliseconds(1));
+            }
+        }
+    }
+}
+
+extern "C" {
+
+iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out) {
+    if (!opts || !out) return IQA_ERR_NULL;
+    if (opts->streams < 1 || opts->streams > 16 || opts->max_batch < 1 ||
+        opts->max_batch > (1 << 20) || opts->hbm_budget_bytes <= 0 ||
+        opts->host_arena_bytes < 0)
+        return IQA_ERR_CONFIG;
+    if (opts->waves != 0 && (opts->waves < 4 || opts->waves % 4 != 0)) return IQA_ERR_CONFIG;
+    auto *sv = new iqa_server();
+    sv->opts = *opts;
+    if (sv->opts.waves == 0) sv->opts.waves = iqa_batch_default_waves();
+    hipError_t e = hipGetDevice(&sv->device);
+    sv->slots.resize(opts->streams);
+    for (Slot &s : sv->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(&s.desc_host, (size_t)opts->max_batch * IQA_BATCH_DESC_BYTES,
+                              hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc(&s.desc_dev, (size_t)opts->max_batch * IQA_BATCH_DESC_BYTES);
+        if (e == hipSuccess && opts->host_arena_bytes > 0) {
+            e = hipMalloc(reinterpret_cast<void **>(&s.arena), (size_t)opts->host_arena_bytes);
+            s.arena_bytes = opts->host_arena_bytes;
+        }
+    }
+    if (e != hipSuccess) {
+        iqa_server_destroy(sv);
+        return IQA_ERR_HIP;
+    }
+    sv->worker = std::thread([sv] { sv->run(); });
+    *out = sv;
+    return IQA_OK;
+}
+
+iqa_status iqa_server_add_reference(iqa_server *sv, const float *ref, int64_t N,
+                                    int32_t *ref_id) {
+    if (!sv || !ref || !ref_id) return IQA_ERR_NULL;
+    if (N <= 0 || N > IQA_MAX_N) return IQA_ERR_SHAPE;
+    if ((reinterpret_cast<uintptr_t>(ref) % 16) != 0) return IQA_ERR_ALIGN;
+    std::lock_guard<std::mutex> lock(sv->mu);
+    if (sv->submitted > 0) return IQA_ERR_CONFIG;   // references are fixed once serving
+    sv->refs.push_back(Ref{ref, N});
+    *ref_id = (int32_t)sv->refs.size() - 1;
+    return IQA_OK;
+}
+
+iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t count) {
+    if (!sv || !reqs) return IQA_ERR_NULL;
+    if (count < 0) return IQA_ERR_SHAPE;
+    const int64_t t = now_ns();
+    std::vector<Pending> ok;
+    ok.reserve(count);
+    int64_t rejected = 0;
+    std::vector<iqa_completion> bad;
+    for (int64_t i = 0; i < count; ++i) {
+        const iqa_request &r = reqs[i];
+        int st = IQA_OK;
+        if (r.ref_id < 0 || r.ref_id >= (int32_t)sv->refs.size()) {
+            st = IQA_ERR_CONFIG;
+        } else {
+            const int64_t N = sv->refs[r.ref_id].N;
+            if (r.NT <= 0 || N % r.NT != 0 || r.NT % 4 != 0) st = IQA_ERR_SHAPE;
+            else if (!r.snapshot_dev == !r.snapshot_host) st = IQA_ERR_NULL;
+            else if (!r.lisi && !r.auglisi && !r.sums) st = IQA_ERR_NULL;
+            else if (r.snapshot_dev && (reinterpret_cast<uintptr_t>(r.snapshot_dev) % 16))
+                st = IQA_ERR_ALIGN;
+            else if (request_cost(*sv, r) > sv->opts.hbm_budget_bytes) st = IQA_ERR_BUDGET;
+            else if (r.snapshot_host &&
+                     ((4 * N * N + 255) & ~int64_t(255)) > sv->opts.host_arena_bytes)
+                st = IQA_ERR_BUDGET;
+        }
+        if (st != IQA_OK) {
+            iqa_completion c{};
+            c.tag = r.tag;
+            c.status = st;
+            c.t_submit_ns = c.t_admit_ns = c.t_launch_ns = c.t_done_ns = t;
+            bad.push_back(c);
+            ++rejected;
+            continue;
+        }
+        Pending p;
+        p.req = r;
+        p.t_submit = t;
+        p.cost = request_cost(*sv, r);
+        ok.push_back(p);
+    }
+    {
+        std::lock_guard<std::mutex> lock(sv->mu);
+        if (sv->stop) return IQA_ERR_CONFIG;
+        for (Pending &p : ok) sv->intake.push_back(p);
+        for (iqa_completion &c : bad) sv->done.push_back(c);
+        sv->submitted += count;
+        sv->completed += rejected;
+        sv->rejected += rejected;
+    }
+    sv->cv.notify_one();
+    sv->cv_done.notify_all();
+    return IQA_OK;
+}
+
+int64_t iqa_server_poll(iqa_server *sv, iqa_completion *out, int64_t max) {
+    if (!sv || !out || max <= 0) return 0;
+    std::lock_guard<std::mutex> lock(sv->mu);
+    int64_t n = 0;
+    while (n < max && !sv->done.empty()) {
+        out[n++] = sv->done.front();
+        sv->done.pop_front();
+    }
+    return n;
+}
+
+iqa_status iqa_server_drain(iqa_server *sv, int64_t timeout_ms) {
+    if (!sv) return IQA_ERR_NULL;
+    std::unique_lock<std::mutex> lock(sv->mu);
+    const bool ok = sv->cv_done.wait_for(lock, std::chrono::milliseconds(timeout_ms),
+                                         [sv] { return sv->completed == sv->submitted; });
+    return ok ? IQA_OK : IQA_ERR_TIMEOUT;
+}
+
+iqa_status iqa_server_get_stats(iqa_server *sv, iqa_server_stats *st) {
+    if (!sv || !st) return IQA_ERR_NULL;
+    std::lock_guard<std::mutex> lock(sv->mu);
+    st->submitted = sv->submitted;
+    st->completed = sv->completed;
+    st->rejected = sv->rejected;
+    st->batches = sv->batches;
+    st->max_batch = sv->max_batch_seen;
+    st->in_flight_bytes = sv->in_flight_bytes;
+    st->peak_in_flight_bytes = sv->peak_in_flight_bytes;
+    st->last_hip_error = sv->last_hip_error;
+    return IQA_OK;
+}
+
+iqa_status iqa_server_replay(iqa_server *sv, const iqa_request *reqs,
+                             const int64_t *arrival_ns, int64_t count, iqa_completion *out,
+                             int64_t timeout_ms) {
+    if (!sv || !reqs || !arrival_ns || !out) return IQA_ERR_NULL;
+    if (count < 0) return IQA_ERR_SHAPE;
+    for (int64_t i = 1; i < count; ++i)
+        if (arrival_ns[i] < arrival_ns[i - 1]) return IQA_ERR_CONFIG;
+    // Open loop: an arrival thread submits request i at start + arrival_ns[i]
+    // whatever the state of the server; this thread collects completions.
+    const int64_t t0 = now_ns() + 1000000;   // 1 ms to get going
+    std::atomic<bool> abort{false};
+    std::thread arrivals([&] {
+        for (int64_t i = 0; i < count && !abort.load(); ++i) {
+            const int64_t due = t0 + arrival_ns[i];
+            while (now_ns() < due) {
+                if (due - now_ns() > 200000) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            }
+            iqa_server_submit(sv, &reqs[i], 1);
+        }
+    });
+    std::vector<iqa_completion> got;
+    got.reserve(count);
+    std::vector<iqa_completion> buf(4096);
+    const int64_t deadline = now_ns() + timeout_ms * 1000000;
+    iqa_status st = IQA_OK;
+    while ((int64_t)got.size() < count) {
+        const int64_t n = iqa_server_poll(sv, buf.data(), (int64_t)buf.size());
+        for (int64_t i = 0; i < n; ++i) got.push_back(buf[i]);
+        if (n == 0) {
+            if (now_ns() > deadline) {
+                st = IQA_ERR_TIMEOUT;
+                abort.store(true);
+                break;
+            }
+            std::this_thread::yield();
+        }
+    }
+    arrivals.join();
+    // Completion order; times relative to the start of the trace.
+    for (int64_t i = 0; i < (int64_t)got.size() && i < count; ++i) {
+        out[i] = got[i];
+        out[i].t_submit_ns -= t0;
+        out[i].t_admit_ns -= t0;
+        out[i].t_launch_ns -= t0;
+        out[i].t_done_ns -= t0;
+    }
+    return st;
+}
+
+iqa_status iqa_server_destroy(iqa_server *sv) {
+    if (!sv) return IQA_ERR_NULL;
+    {
+        std::lock_guard<std::mutex> lock(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    for (Slot &s : sv->slots) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.desc_host) (void)hipHostFree(s.desc_host);
+        if (s.desc_dev) (void)hipFree(s.desc_dev);
+        if (s.arena) (void)hipFree(s.arena);
+    }
+    delete sv;
+    return IQA_OK;
+}
+
+}  // extern "C"

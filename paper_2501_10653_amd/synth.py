@@ -53,7 +53,7 @@ class PairSpec:
 
 
 # Constants of the similarity indices: the paper only requires them to be much
-# smaller than one; 1e-6 is used for every workload (see the design doc readings).
+# smaller than one; 1e-6 is used for every workload.
 C_DEFAULT = 1e-6
 
 
@@ -179,3 +179,37 @@ def random_pair(N: int, rng: np.random.Generator, neg_frac: float = 0.3,
         x[rng.uniform(size=(N, N)) < nan_frac] = np.nan
         y[rng.uniform(size=(N, N)) < nan_frac] = np.nan
     return x.astype(np.float32), y.astype(np.float32)
+
+
+_STREAM_SNAPSHOT = 10
+
+
+def serving_references(count: int = 16, Ns: Sequence[int] = (1024, 2048, 4096),
+                       seed: int = 11) -> List[PairSpec]:
+    """Resident references for the serving workload: N assigned round-robin
+    over Ns; each reference is the all-sources image of a pair whose later
+    snapshots lose the faintest sources (scaled by area, at least one)."""
+    out = []
+    for r in range(count):
+        N = int(Ns[r % len(Ns)])
+        out.append(PairSpec(N=N, NT=64, n_src=scaled_count(33, N, 1), amp_lo=1e-3, amp_hi=2.0,
+                            fwhm=4.0, noise_sigma=1e-4, n_drop=scaled_count(5, N, 1),
+                            seed=seed * 1000 + r))
+    return out
+
+
+def make_snapshot(spec: PairSpec, k: int) -> np.ndarray:
+    """Snapshot k of a reference: the kept sources re-rendered with noise from
+    an independent stream per k (the reference itself is make_pair(spec)[0])."""
+    rows, cols, amps = _source_list(spec)
+    keep = np.arange(spec.n_src) >= spec.n_drop
+    img = render_sources(spec.N, rows[keep], cols[keep], amps[keep], spec.fwhm)
+    img += _noise(spec.N, spec.noise_sigma, spec.seed, _STREAM_SNAPSHOT + k)
+    return np.ascontiguousarray(img, dtype=np.float32)
+
+
+def poisson_arrivals(rate: float, count: int, seed: int = 0) -> np.ndarray:
+    """Open-loop arrival times (ns from the start) of a Poisson process."""
+    rng = np.random.default_rng((seed, 77))
+    gaps = rng.exponential(1.0 / rate, count)
+    return np.cumsum(gaps * 1e9).astype(np.int64)

@@ -1,0 +1,252 @@
+"""Autotuner for the launch shapes of the tile kernels.
+
+For a single image pair of shape (N, N_T) it times every valid candidate
+launch configuration (waves per workgroup, rows per load batch, row phases per
+wave, workgroups per tile) and keeps the fastest.  For ragged batches it
+picks, per N_T, the per-pair geometry (row phases per wave) and the number of
+persistent waves.  Timing replays a HIP graph of K launches that rotate over a
+pool of distinct device copies of the pair (more bytes than the 256 MB
+Infinity Cache), so every launch streams from HBM.
+
+Results go to a JSON cache (``tuned/gfx950.json`` next to this file), which
+the build embeds into the library as its default shapes.
+
+    python -m paper_2501_10653_amd.tune --sweep --batch --out paper_2501_10653_amd/tuned/gfx950.json
+"""
+
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tuned", "gfx950.json")
+
+SWEEP = [(N, NT) for N in (1024, 2048, 4096, 8192) for NT in (16, 32, 64, 128, 256)]
+EXTRA = [(256, 32), (512, 32), (512, 64), (512, 128), (1024, 512), (2048, 512), (4096, 512)]
+
+
+def candidates_single(N: int, NT: int, max_waves_total: int = 1 << 17) -> List[dict]:
+    """Valid vec-4 configurations worth timing for (N, NT)."""
+    from .iqa import check_cfg
+    if NT % 4:
+        return []
+    lpt = NT // 4
+    seg = min(64, 1 << (lpt - 1).bit_length())
+    tpw = 64 // seg
+    ns = N // NT
+    out = []
+    combos = [(w, u) for w in (1, 2, 4, 8) for u in (4, 8)] + [(16, 4)]
+    for (waves, unroll), rp_log, ks_log in itertools.product(combos, range(7), range(10)):
+        rp, ks = 1 << rp_log, 1 << ks_log
+        if rp > tpw:
+            continue
+        cfg = dict(vec=4, waves=waves, unroll=unroll, seg=seg, rp=rp, ksplit=ks)
+        if check_cfg(N, NT, cfg) != 0:
+            continue
+        ht = tpw // rp
+        total = ns * math.ceil(ns / ht) * ks * waves
+        rows_per_lane = NT / (rp * waves * ks)
+        if total < 128 or total > max_waves_total or rows_per_lane < 2:
+            continue
+        out.append(cfg)
+    return out
+
+
+class _Timer:
+    """Graph-replay timing on one stream with a rotating pool of pairs."""
+
+    def __init__(self, torch, stream):
+        self.torch = torch
+        self.stream = stream
+
+    def per_launch_us(self, launch, K: int, reps: int = 5) -> float:
+        torch = self.torch
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=self.stream):
+            for i in range(K):
+                launch(i)
+        with torch.cuda.stream(self.stream):
+            g.replay()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            e0.record(self.stream)
+            with torch.cuda.stream(self.stream):
+                g.replay()
+            e1.record(self.stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / K * 1e3)
+        del g
+        return float(np.median(ts))
+
+
+def _pool(torch, dev, N: int, NT: int, pool_bytes: float):
+    from . import synth
+    x, y, _ = synth.make_pair(synth.spec_sweep(N, NT))
+    n = max(2, int(math.ceil(pool_bytes / (8 * N * N))))
+    xs = [torch.from_numpy(x).to(dev)]
+    ys = [torch.from_numpy(y).to(dev)]
+    for _ in range(n - 1):
+        xs.append(xs[0].clone())
+        ys.append(ys[0].clone())
+    return xs, ys
+
+
+def tune_single(N: int, NT: int, pool_bytes: float = 2 ** 30, K: int = 64,
+                log=None) -> Tuple[dict, float, List[Tuple[float, dict]]]:
+    """Time every candidate for (N, NT); returns (best cfg, best us, all)."""
+    import torch
+    from .iqa import default_cfg, iqa_tiles, prepare
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream(dev)
+    xs, ys = _pool(torch, dev, N, NT, pool_bytes)
+    ns = N // NT
+    out = {"lisi": torch.empty(ns, ns, device=dev), "auglisi": torch.empty(ns, ns, device=dev)}
+    timer = _Timer(torch, s)
+    pool = len(xs)
+    K = max(K, pool)
+    results = []
+    cands = candidates_single(N, NT)
+    base = default_cfg(N, NT)
+    if base not in cands:
+        cands.append(base)
+    for cfg in cands:
+        prepare(N, NT, cfg, stream=s)
+        us = timer.per_launch_us(
+            lambda i: iqa_tiles(xs[i % pool], ys[i % pool], NT, out=out, cfg=cfg, stream=s), K)
+        results.append((us, cfg))
+        if log:
+            log(f"  {N}/{NT} {us:8.2f} us {cfg}")
+    results.sort(key=lambda r: r[0])
+    del xs, ys
+    torch.cuda.empty_cache()
+    return results[0][1], results[0][0], results
+
+
+def candidates_batch(NT: int) -> List[dict]:
+    lpt = NT // 4
+    seg = min(64, 1 << (lpt - 1).bit_length())
+    tpw = 64 // seg
+    return [dict(vec=4, waves=1, unroll=8, seg=seg, rp=1 << r, ksplit=1)
+            for r in range(7) if (1 << r) <= tpw]
+
+
+def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 1024, 2048, 4096),
+               copies: int = 8, waves_list: Sequence[int] = (1024, 2048, 4096),
+               log=None) -> Tuple[Dict[int, dict], int, list]:
+    """Per-N_T batch geometry and the persistent wave count, timed on a batch
+    of `copies` pairs of every (N, N_T)."""
+    import torch
+    from . import _lib, synth
+    from ._lib import LaunchCfg
+    from .batch import Batch
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream(dev)
+    timer = _Timer(torch, s)
+    proto = {}
+    for N in Ns:
+        x, y, _ = synth.make_pair(synth.spec_sweep(N, 64))
+        proto[N] = (torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev))
+    lib = _lib.load()
+    best: Dict[int, dict] = {}
+    log_rows = []
+    for NT in NTs:
+        pairs = [(proto[N][0].clone(), proto[N][1].clone(), NT) for N in Ns for _ in range(copies)]
+        total = sum(8 * p[0].shape[0] ** 2 for p in pairs)
+        res = []
+        for cfg in candidates_batch(NT):
+            for N in Ns:
+                _lib.check(lib.iqa_tune_set(N, NT, _lib.TUNE_BATCH,
+                                            LaunchCfg.from_dict(cfg)), "iqa_tune_set")
+            b = Batch(pairs, waves=2048)
+            us = timer.per_launch_us(lambda i: b.run(stream=s), 4)
+            res.append((us, cfg))
+            log_rows.append({"NT": NT, "cfg": cfg, "us": us, "gbs": total / us / 1e3})
+            if log:
+                log(f"  batch NT={NT} {us:9.1f} us {total / us / 1e3:7.0f} GB/s {cfg}")
+        res.sort(key=lambda r: r[0])
+        best[NT] = res[0][1]
+        for N in Ns:
+            lib.iqa_tune_set(N, NT, _lib.TUNE_BATCH, LaunchCfg.from_dict(best[NT]))
+        del pairs
+    # persistent waves on the mixed batch
+    mixed = [(proto[N][0].clone(), proto[N][1].clone(), NT) for N in Ns for NT in NTs
+             for _ in range(max(1, copies // 2))]
+    total = sum(8 * p[0].shape[0] ** 2 for p in mixed)
+    wres = []
+    for w in waves_list:
+        b = Batch(mixed, waves=w)
+        us = timer.per_launch_us(lambda i: b.run(stream=s), 4)
+        wres.append((us, w))
+        log_rows.append({"NT": "mixed", "waves": w, "us": us, "gbs": total / us / 1e3})
+        if log:
+            log(f"  batch mixed waves={w} {us:9.1f} us {total / us / 1e3:7.0f} GB/s")
+    wres.sort()
+    lib.iqa_tune_clear()
+    return best, wres[0][1], log_rows
+
+
+def load(path: str = DEFAULT_OUT) -> Optional[dict]:
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--shapes", default="", help="comma list of N:NT")
+    ap.add_argument("--sweep", action="store_true", help="the N x N_T size-sweep grid")
+    ap.add_argument("--batch", action="store_true", help="tune ragged-batch geometry")
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--K", type=int, default=64)
+    args = ap.parse_args(argv)
+    import torch
+
+    shapes = []
+    if args.sweep:
+        shapes += SWEEP + EXTRA
+    for item in filter(None, args.shapes.split(",")):
+        N, NT = (int(v) for v in item.split(":"))
+        shapes.append((N, NT))
+    doc = load(args.out) or {}
+    doc.setdefault("arch", torch.cuda.get_device_properties(0).gcnArchName.split(":")[0])
+    doc.setdefault("single", {})
+    t0 = time.time()
+
+    def log(msg):
+        print(msg, flush=True)
+
+    for N, NT in shapes:
+        cfg, us, res = tune_single(N, NT, K=args.K)
+        doc["single"][f"{N}x{NT}"] = {"cfg": cfg, "us": round(us, 3),
+                                      "gbs": round(8 * N * N / us / 1e3, 1),
+                                      "runner_up": [{"cfg": c, "us": round(u, 3)}
+                                                    for u, c in res[1:4]]}
+        log(f"{N}/{NT}: best {us:.2f} us ({8 * N * N / us / 1e3:.0f} GB/s) {cfg}")
+    if args.batch:
+        best, waves, rows = tune_batch(log=log)
+        doc["batch"] = {str(NT): cfg for NT, cfg in best.items()}
+        doc["batch_waves"] = waves
+        doc["batch_log"] = rows
+    doc["tuned_at_s"] = round(time.time() - t0, 1)
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    with open(args.out, "w") as fh:
+        json.dump(doc, fh, indent=1, sort_keys=True)
+    log(f"wrote {args.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -17,7 +17,7 @@ from paper_2501_10653_amd._lib import LaunchCfg
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "iqa.h")
 
-OK, NULL, SHAPE, ALIGN, PARAM, HIP, CONFIG, CAPTURE = range(8)
+OK, NULL, SHAPE, ALIGN, PARAM, HIP, CONFIG, CAPTURE, BUDGET, TIMEOUT = range(10)
 FAKE = 1 << 20          # 16-byte-aligned stand-in for a device pointer (never dereferenced)
 C6 = 1e-6
 
@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = _lib.load()
-    for s in range(8):
+    for s in range(10):
         assert lib.iqa_status_str(s).decode().startswith(_lib.STATUS_NAMES[s])
     assert b"unknown" in lib.iqa_status_str(99)
     assert lib.iqa_version() >= 100
@@ -144,8 +144,11 @@ def test_batch_describe_validates_every_pair(over, status):
     st = _lib.load().iqa_batch_describe(arr, 3, buf.ctypes.data, ctypes.byref(units))
     assert st == status
     if status == OK:
-        # 256/32: 8x8 tiles, 8 tiles per wave -> 8 units per pair
-        assert units.value == 3 * 8
+        # one unit per tile group: 8 rows of tiles x ceil(8 / tiles-per-wave)
+        c = LaunchCfg()
+        assert _lib.load().iqa_batch_cfg(256, 32, ctypes.byref(c)) == OK
+        ht = 64 // (c.seg * c.rp)
+        assert units.value == 3 * 8 * -(-8 // ht)
 
 
 def test_batch_launch_validation():
@@ -159,6 +162,8 @@ def test_batch_launch_validation():
 
 def test_tune_registry():
     lib = _lib.load()
+    lib.iqa_tune_clear()
+    baseline = default_cfg(2048, 64)[1]
     try:
         good = LaunchCfg.from_dict(dict(vec=4, waves=1, unroll=8, seg=16, rp=2, ksplit=1))
         assert lib.iqa_tune_set(2048, 64, _lib.TUNE_SINGLE, ctypes.byref(good)) == OK
@@ -169,23 +174,27 @@ def test_tune_registry():
         assert lib.iqa_tune_set(2048, 64, _lib.TUNE_BATCH, ctypes.byref(good)) == OK
         c2 = LaunchCfg()
         assert lib.iqa_batch_cfg(2048, 64, ctypes.byref(c2)) == OK and c2.as_dict() == good.as_dict()
+        # N == 0 registers for every N with this NT
+        wide = LaunchCfg.from_dict(dict(vec=4, waves=1, unroll=8, seg=16, rp=4, ksplit=1))
+        assert lib.iqa_tune_set(0, 64, _lib.TUNE_BATCH, ctypes.byref(wide)) == OK
+        assert lib.iqa_batch_cfg(4096, 64, ctypes.byref(c2)) == OK and c2.as_dict() == wide.as_dict()
         bad = LaunchCfg.from_dict(dict(vec=4, waves=2, unroll=8, seg=16, rp=2, ksplit=1))
         assert lib.iqa_tune_set(2048, 64, _lib.TUNE_BATCH, ctypes.byref(bad)) == CONFIG
         assert lib.iqa_tune_set(2048, 64, 7, ctypes.byref(good)) == CONFIG
         assert lib.iqa_tune_set(2048, 63, 0, ctypes.byref(good)) == SHAPE
     finally:
         lib.iqa_tune_clear()
-    assert default_cfg(2048, 64)[1]["rp"] == 4   # built-in choice again
+    assert default_cfg(2048, 64)[1] == baseline
+    assert lib.iqa_batch_default_waves() >= 4
 
 
-@pytest.mark.parametrize("args,status", [
-    (dict(sums_in=None), NULL), (dict(ns=8, f=3), SHAPE), (dict(f=0), SHAPE), (dict(ns=0), SHAPE),
-    (dict(lisi=None, aug=None, out=None), NULL), (dict(sums_in=FAKE + 4), ALIGN),
-    (dict(C=0.0), PARAM), (dict(D=float("nan")), PARAM),
-])
-def test_merge_validation(args, status):
-    kw = dict(sums_in=FAKE, ns=8, f=2, D=C6 / 2, C2=C6, C=C6, lisi=FAKE, aug=FAKE, out=None)
-    kw.update(args)
-    st = _lib.load().iqa_merge_tiles(kw["sums_in"], kw["ns"], kw["f"], kw["D"], kw["C2"], kw["C"],
-                                     kw["lisi"], kw["aug"], kw["out"], None)
-    assert st == status
+@pytest.mark.parametrize("over", [dict(streams=0), dict(streams=17), dict(max_batch=0),
+                                  dict(hbm_budget_bytes=0), dict(waves=6), dict(host_arena_bytes=-1)])
+def test_server_options_validated_before_any_gpu_call(over):
+    kw = dict(hbm_budget_bytes=1 << 30, host_arena_bytes=0, waves=0, streams=2, max_batch=64,
+              D=C6 / 2, C1=C6, C2=C6, C=C6)
+    kw.update(over)
+    opts = _lib.ServerOpts(**kw)
+    h = ctypes.c_void_p()
+    assert _lib.load().iqa_server_create(ctypes.byref(opts), ctypes.byref(h)) == CONFIG
+    assert not h.value
