@@ -306,6 +306,15 @@ typedef struct iqa_server_stats {
  * buffer cannot be created. */
 iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out);
 
+/* Dry run, for capacity planning and for testing the scheduling policy
+ * without a GPU: a server that admits, batches and retires requests exactly
+ * like iqa_server_create's but launches nothing and makes no HIP call.  A
+ * batch of b input bytes completes fixed_ns + b / bytes_per_ns nanoseconds
+ * after its launch; outputs are not written.  Reference and snapshot pointers
+ * are only checked for alignment, never dereferenced. */
+iqa_status iqa_server_create_dry(const iqa_server_opts *opts, int64_t fixed_ns,
+                                 double bytes_per_ns, iqa_server **out);
+
 /* Register a resident reference (device, N x N, 16-byte aligned, owned by the
  * caller and kept alive until iqa_server_destroy).  Only before the first
  * submit. */

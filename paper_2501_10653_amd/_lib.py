@@ -138,6 +138,8 @@ def load() -> ctypes.CDLL:
                                ctypes.c_int),
         "iqa_tiles_batched": ([vp, i64, i64, i64, vp], ctypes.c_int),
         "iqa_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], ctypes.c_int),
+        "iqa_server_create_dry": ([ctypes.POINTER(ServerOpts), i64, ctypes.c_double,
+                                   ctypes.POINTER(vp)], ctypes.c_int),
         "iqa_server_add_reference": ([vp, vp, i64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "iqa_server_submit": ([vp, ctypes.POINTER(Request), i64], ctypes.c_int),
         "iqa_server_poll": ([vp, ctypes.POINTER(Completion), i64], ctypes.c_int64),

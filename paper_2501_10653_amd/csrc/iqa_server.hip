@@ -61,6 +61,7 @@ struct Slot {
     bool busy = false;
     int64_t t_launch = 0;
     int64_t bytes = 0;           // budget held by this batch
+    int64_t dry_due = 0;         // dry run: when the simulated batch completes
     std::vector<Pending> reqs;
 };
 
@@ -69,6 +70,11 @@ struct Slot {
 struct iqa_server {
     iqa_server_opts opts{};
     int device = 0;
+    // Dry run: schedule exactly as below but launch nothing; a batch of b
+    // bytes completes dry_fixed_ns + b / dry_bytes_per_ns after its launch.
+    bool dry = false;
+    int64_t dry_fixed_ns = 0;
+    double dry_bytes_per_ns = 1.0;
     std::vector<Ref> refs;
     std::vector<Slot> slots;
 
@@ -103,6 +109,15 @@ int64_t request_cost(const iqa_server &sv, const iqa_request &r) {
 }  // namespace
 
 bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
+    if (dry) {
+        int64_t bytes = 0;
+        for (const Pending &p : batch) bytes += 8 * refs[p.req.ref_id].N * refs[p.req.ref_id].N;
+        s.reqs.swap(batch);
+        s.busy = true;
+        s.t_launch = now_ns();
+        s.dry_due = s.t_launch + dry_fixed_ns + (int64_t)((double)bytes / dry_bytes_per_ns);
+        return true;
+    }
     std::vector<iqa_pair> pairs(batch.size());
     int64_t arena_off = 0;
     bool ok = true;
@@ -178,7 +193,7 @@ void iqa_server::retire(Slot &s, int status) {
 }
 
 void iqa_server::run() {
-    (void)hipSetDevice(device);
+    if (!dry) (void)hipSetDevice(device);
     const int64_t budget = opts.hbm_budget_bytes;
     std::vector<Pending> batch;
     while (true) {
@@ -198,6 +213,13 @@ void iqa_server::run() {
         // Retire finished batches.
         for (Slot &s : slots) {
             if (!s.busy) continue;
+            if (dry) {
+                if (now_ns() >= s.dry_due) {
+                    retire(s, IQA_OK);
+                    idle = false;
+                }
+                continue;
+            }
             const hipError_t q = hipEventQuery(s.done);
             if (q == hipSuccess) {
                 retire(s, IQA_OK);
@@ -241,7 +263,7 @@ void iqa_server::run() {
             s.bytes = add;
             if (!launch(s, batch)) {
                 // Let whatever was enqueued finish before the slot is reused.
-                (void)hipStreamSynchronize(s.stream);
+                if (!dry) (void)hipStreamSynchronize(s.stream);
                 retire(s, IQA_ERR_HIP);
             }
             idle = false;
@@ -262,13 +284,19 @@ void iqa_server::run() {
 
 extern "C" {
 
-iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out) {
-    if (!opts || !out) return IQA_ERR_NULL;
+static iqa_status check_opts(const iqa_server_opts *opts) {
     if (opts->streams < 1 || opts->streams > 16 || opts->max_batch < 1 ||
         opts->max_batch > (1 << 20) || opts->hbm_budget_bytes <= 0 ||
         opts->host_arena_bytes < 0)
         return IQA_ERR_CONFIG;
     if (opts->waves != 0 && (opts->waves < 4 || opts->waves % 4 != 0)) return IQA_ERR_CONFIG;
+    return IQA_OK;
+}
+
+iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out) {
+    if (!opts || !out) return IQA_ERR_NULL;
+    iqa_status st = check_opts(opts);
+    if (st != IQA_OK) return st;
     auto *sv = new iqa_server();
     sv->opts = *opts;
     if (sv->opts.waves == 0) sv->opts.waves = iqa_batch_default_waves();
@@ -291,6 +319,24 @@ iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out) {
         iqa_server_destroy(sv);
         return IQA_ERR_HIP;
     }
+    sv->worker = std::thread([sv] { sv->run(); });
+    *out = sv;
+    return IQA_OK;
+}
+
+iqa_status iqa_server_create_dry(const iqa_server_opts *opts, int64_t fixed_ns,
+                                 double bytes_per_ns, iqa_server **out) {
+    if (!opts || !out) return IQA_ERR_NULL;
+    iqa_status st = check_opts(opts);
+    if (st != IQA_OK) return st;
+    if (fixed_ns < 0 || !(bytes_per_ns > 0.0)) return IQA_ERR_CONFIG;
+    auto *sv = new iqa_server();
+    sv->opts = *opts;
+    sv->dry = true;
+    sv->dry_fixed_ns = fixed_ns;
+    sv->dry_bytes_per_ns = bytes_per_ns;
+    sv->slots.resize(opts->streams);
+    for (Slot &s : sv->slots) s.arena_bytes = opts->host_arena_bytes;
     sv->worker = std::thread([sv] { sv->run(); });
     *out = sv;
     return IQA_OK;

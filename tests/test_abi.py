@@ -198,3 +198,20 @@ def test_server_options_validated_before_any_gpu_call(over):
     h = ctypes.c_void_p()
     assert _lib.load().iqa_server_create(ctypes.byref(opts), ctypes.byref(h)) == CONFIG
     assert not h.value
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """A C program built with gcc against include/iqa.h links to the library
+    and gets the documented statuses back."""
+    exe = tmp_path / "c_abi_check"
+    src = os.path.join(ROOT, "tests", "c_abi_check.c")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    src, "-o", str(exe), "-L", libdir, "-l:libiqa_hip.so",
+                    f"-Wl,-rpath,{libdir}"], check=True, capture_output=True)
+    res = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stdout + res.stderr
+    sizes = [int(v) for v in res.stdout.split("sizes")[1].split("\n")[0].split()]
+    mirrors = [LaunchCfg, _lib.IqaPair, _lib.ServerOpts, _lib.Request, _lib.Completion,
+               _lib.ServerStats]
+    assert sizes == [ctypes.sizeof(m) for m in mirrors]
