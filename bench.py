@@ -57,7 +57,9 @@ def parse_args(argv=None):
                     help="Poisson request rate of the serving leg of the default run (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--rates", default="2000,5000,10000,20000,50000",
-                    help="request rates of --workload serve")
+                    help="request rates of --workload serve (device-resident snapshots)")
+    ap.add_argument("--h2d-rates", default="500,1000,2000",
+                    help="request rates of --workload serve with pinned host snapshots")
     return ap.parse_args(argv)
 
 
@@ -144,32 +146,44 @@ class ServingWorld:
             self.refs.append(torch.from_numpy(x).to(dev))
             self.snaps.append([torch.from_numpy(synth.make_snapshot(sp, k)).to(dev)
                                for k in range(snapshots_per_ref)])
+        self.host_snaps = None
 
-    def requests(self, srv, ids, count: int, seed: int):
+    def pin_snapshots(self):
+        """Pinned host copies of the snapshots, for the H2D serving mode."""
+        if self.host_snaps is None:
+            self.host_snaps = [[s.cpu().pin_memory() for s in per] for per in self.snaps]
+
+    def requests(self, srv, ids, count: int, seed: int, host: bool = False):
         rng = np.random.default_rng((seed, 3))
         out, nbytes = [], 0
+        snaps = self.host_snaps if host else self.snaps
         for i in range(count):
             r = int(rng.integers(len(self.refs)))
-            k = int(rng.integers(len(self.snaps[r])))
+            k = int(rng.integers(len(snaps[r])))
             NT = int(rng.choice([32, 64]))
-            out.append(srv.request(self.snaps[r][k], ids[r], NT))
+            out.append(srv.request(snaps[r][k], ids[r], NT))
             nbytes += 8 * self.specs[r].N ** 2
         return out, nbytes
 
 
 def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 30,
-                streams: int = 2, max_batch: int = 512, seed: int = 0) -> dict:
+                streams: int = 2, max_batch: int = 512, seed: int = 0,
+                host: bool = False) -> dict:
     from paper_2501_10653_amd import synth
     from paper_2501_10653_amd.serve import Server, latency_summary
     count = max(200, int(rate * seconds))
-    with Server(budget, streams=streams, max_batch=max_batch) as srv:
+    arena = (2 << 30) if host else 0
+    if host:
+        world.pin_snapshots()
+    with Server(budget, streams=streams, max_batch=max_batch, host_arena_bytes=arena) as srv:
         ids = [srv.add_reference(r) for r in world.refs]
-        reqs, nbytes = world.requests(srv, ids, count, seed)
+        reqs, nbytes = world.requests(srv, ids, count, seed, host=host)
         arrivals = synth.poisson_arrivals(rate, count, seed=seed)
         comps = srv.replay(reqs, arrivals, timeout_s=120.0)
         st = srv.stats()
     summ = latency_summary(comps)
     summ.update({"offered_rps": rate, "requests": count, "batches": st["batches"],
+                 "snapshots": "pinned host (H2D per request)" if host else "device-resident",
                  "max_batch": st["max_batch"],
                  "peak_in_flight_MiB": round(st["peak_in_flight_bytes"] / 2 ** 20, 1),
                  "budget_GiB": budget / 2 ** 30, "streams": streams,
@@ -287,6 +301,8 @@ def main(argv=None) -> int:
         world = ServingWorld(torch, dev)
         rows = [run_serving(torch, world, float(r), args.serve_seconds, seed=i)
                 for i, r in enumerate(args.rates.split(","))]
+        rows += [run_serving(torch, world, float(r), args.serve_seconds, seed=100 + i, host=True)
+                 for i, r in enumerate(args.h2d_rates.split(",")) if r]
         print(json.dumps({"metric": "p99 request latency (serving, device-resident snapshots)",
                           "unit": "us", "higher_is_better": False, "n_gpus": 1,
                           "data": "synthetic",

@@ -36,9 +36,11 @@
  *   workgroups whose partial sums a second, small kernel combines on the same
  *   stream; those launches use a small library-owned device workspace per
  *   (device, stream) (16 bytes per tile and split part), allocated on first
- *   use and reused afterwards.  The first call for a given (device, stream,
- *   shape) must therefore not happen while the stream is being captured into
- *   a graph: call iqa_prepare() (or the entry point itself) once before.
+ *   use and reused afterwards (an outgrown buffer is kept until the process
+ *   ends, so graphs captured earlier stay valid).  The first call for a given
+ *   (device, stream, shape) must therefore not happen while the stream is
+ *   being captured into a graph: call iqa_prepare() (or the entry point
+ *   itself) once before.
  * Errors.  Every entry point validates its arguments before touching the GPU
  *   and returns a status; nothing is launched when the status is not IQA_OK.
  *   Launch failures are reported as IQA_ERR_HIP, with the HIP error code

@@ -24,6 +24,11 @@
  *   - D, C1, C2, C are caller parameters; callers that want LISI(x,x) ~ 1
  *     pass D = C1/2 (the only choice for which identical inputs give ~1).
  *
+ * Parity status: both functions are pinned by tests/test_oracle.py (worked
+ * examples derived by hand, exact-rational brute force, closed forms,
+ * invariants and the Eq. 3/4 identities), and tests/test_oracle_mutants.py
+ * shows those pins catch planted slips.
+ *
  * Every sum is accumulated in double, pixel by pixel, in row-major order
  * within the tile; no blocking or reordering beyond the definition.  Tile rows
  * may run on several threads (OpenMP) because tiles are independent; the

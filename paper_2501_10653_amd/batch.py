@@ -38,9 +38,10 @@ class Batch:
     """A planned ragged batch.
 
     ``pairs`` is a sequence of ``(x, y, NT)`` with x, y contiguous float32
-    N x N device tensors (16-byte aligned, NT % 4 == 0).  Output tensors are
-    allocated here and reused by every run: ``results[i]`` is the
-    :class:`TileResult` of pair i.
+    N x N device tensors.  Pairs with NT % 4 == 0 and 16-byte aligned images go
+    into the persistent launch; any others are launched one by one on the same
+    stream.  Output tensors are allocated here and reused by every run:
+    ``results[i]`` is the :class:`TileResult` of pair i.
     """
 
     def __init__(self, pairs: Sequence, *, C1: float = C_DEFAULT, C2: float = C_DEFAULT,
@@ -50,12 +51,13 @@ class Batch:
             raise ValueError("empty batch")
         if D is None:
             D = default_D(C1)
+        self.consts = dict(C1=C1, C2=C2, C=C, D=D)
         self.device = device or pairs[0][0].device
         self.waves = int(waves) if waves is not None else default_waves()
         self.inputs = []
         self.results: List[TileResult] = []
-        arr = (IqaPair * len(pairs))()
         self.bytes = 0
+        batched, self.single = [], []      # pairs the persistent kernel takes / does not
         for i, (x, y, NT) in enumerate(pairs):
             N = _check_images(x, y)
             ns = N // NT if NT > 0 and N % NT == 0 else 0
@@ -64,23 +66,46 @@ class Batch:
             so = torch.empty(ns * ns, 4, device=self.device) if sums else None
             self.inputs.append((x, y, NT))
             self.results.append(TileResult(lo, ao, so))
-            arr[i] = IqaPair(x.data_ptr(), y.data_ptr(), N, NT, D, C1, C2, C, lo.data_ptr(),
-                             ao.data_ptr(), so.data_ptr() if so is not None else None)
             self.bytes += 8 * N * N
-        host = np.zeros(len(pairs) * _lib.BATCH_DESC_BYTES, np.uint8)
-        units = ctypes.c_int64(0)
-        _lib.check(_lib.load().iqa_batch_describe(arr, len(pairs), host.ctypes.data,
-                                                  ctypes.byref(units)), "iqa_batch_describe")
-        self.count = len(pairs)
-        self.units = int(units.value)
-        self.descs = torch.from_numpy(host).to(self.device)   # device copy, 256-B aligned
+            vec4 = NT % 4 == 0 and x.data_ptr() % 16 == 0 and y.data_ptr() % 16 == 0
+            (batched if vec4 else self.single).append(i)
+        self.count = len(batched)
+        self.units = 0
+        self.descs = None
+        if batched:
+            arr = (IqaPair * len(batched))()
+            for k, i in enumerate(batched):
+                x, y, NT = self.inputs[i]
+                r = self.results[i]
+                arr[k] = IqaPair(x.data_ptr(), y.data_ptr(), x.shape[0], NT, D, C1, C2, C,
+                                 r.lisi.data_ptr(), r.auglisi.data_ptr(),
+                                 r.sums.data_ptr() if r.sums is not None else None)
+            host = np.zeros(len(batched) * _lib.BATCH_DESC_BYTES, np.uint8)
+            units = ctypes.c_int64(0)
+            _lib.check(_lib.load().iqa_batch_describe(arr, len(batched), host.ctypes.data,
+                                                      ctypes.byref(units)), "iqa_batch_describe")
+            self.units = int(units.value)
+            self.descs = torch.from_numpy(host).to(self.device)   # device copy, 256-B aligned
 
     def run(self, stream=None) -> None:
-        """Enqueue one persistent launch over the whole batch."""
+        """Enqueue the batch: one persistent launch over every pair with
+        N_T % 4 == 0 and 16-byte aligned images, and a single-pair launch for
+        each of the others, all on the same stream."""
+        from .iqa import iqa_tiles
         with torch.cuda.device(self.device):
-            st = _lib.load().iqa_tiles_batched(self.descs.data_ptr(), self.count, self.units,
-                                               self.waves, _stream_handle(self.device, stream))
-        _lib.check(st, "iqa_tiles_batched")
+            if self.descs is not None:
+                st = _lib.load().iqa_tiles_batched(self.descs.data_ptr(), self.count, self.units,
+                                                   self.waves,
+                                                   _stream_handle(self.device, stream))
+                _lib.check(st, "iqa_tiles_batched")
+            for i in self.single:
+                x, y, NT = self.inputs[i]
+                r = self.results[i]
+                out = {"lisi": r.lisi, "auglisi": r.auglisi}
+                if r.sums is not None:
+                    out["sums"] = r.sums
+                iqa_tiles(x, y, NT, sums=r.sums is not None, out=out, stream=stream,
+                          **self.consts)
 
     def capture(self, stream: Optional[torch.cuda.Stream] = None) -> torch.cuda.CUDAGraph:
         """Capture one run into a HIP graph; replay it with ``graph.replay()``

@@ -40,6 +40,7 @@
 #include <mutex>
 #include <tuple>
 #include <utility>
+#include <vector>
 
 #include "iqa.h"
 
@@ -873,13 +874,16 @@ iqa_launch_cfg batch_cfg(int64_t N, int64_t NT) {
 
 // Per (device, stream) workspace for split partials.  Partials are written by
 // tiles_kernel and read by combine_kernel in the same stream order, so one
-// buffer per stream is enough; concurrent streams get their own.
+// buffer per stream is enough; concurrent streams get their own.  A buffer
+// that is outgrown is kept, not freed: a graph captured earlier may still
+// launch kernels that use it.
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
 };
 std::mutex g_ws_mutex;
 std::map<std::pair<int, void *>, Workspace> g_ws;
+std::vector<void *> g_ws_retired;
 
 iqa_status workspace_for(hipStream_t s, size_t bytes, float **out) {
     int dev = 0;
@@ -907,11 +911,7 @@ iqa_status workspace_for(hipStream_t s, size_t bytes, float **out) {
             g_last_hip_error = (int)e;
             return IQA_ERR_HIP;
         }
-        if (w.ptr) {
-            // Earlier launches on this stream may still use the old buffer.
-            (void)hipStreamSynchronize(s);
-            (void)hipFree(w.ptr);
-        }
+        if (w.ptr) g_ws_retired.push_back(w.ptr);
         w.ptr = p;
         w.bytes = nb;
     }

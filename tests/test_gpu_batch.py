@@ -103,3 +103,22 @@ def test_paper_recipe_pairs_in_a_batch():
     torch.cuda.synchronize()
     for (x, y, NT), res in zip(host, b.results):
         assert_parity(res, oracle_for(x, y, NT), what=f"{x.shape[0]}/{NT}")
+
+
+def test_batch_with_pairs_the_persistent_kernel_cannot_take():
+    """N_T not a multiple of 4, and an image 4 bytes off a 16-byte boundary,
+    are launched singly inside Batch.run; every result matches the oracle."""
+    rng = np.random.default_rng(31)
+    host, dev = [], []
+    for N, NT, off in [(300, 12, 0), (90, 6, 0), (81, 9, 0), (256, 32, 1), (512, 64, 0)]:
+        x, y = synth.random_pair(N, rng, neg_frac=0.3, scale=1.0)
+        xd = torch.zeros(N * N + 4, device="cuda")[off:off + N * N].view(N, N)
+        xd.copy_(to_dev(x))
+        host.append((x, y, NT))
+        dev.append((xd, to_dev(y), NT))
+    b = Batch(dev, sums=True)
+    assert sorted(b.single) == [1, 2, 3]
+    b.run()
+    torch.cuda.synchronize()
+    for (x, y, NT), res in zip(host, b.results):
+        assert_parity(res, oracle_for(x, y, NT), what=f"{x.shape[0]}/{NT}")

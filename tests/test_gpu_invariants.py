@@ -163,3 +163,56 @@ def test_invalid_arguments_raise():
         iqa_tiles(xd.double(), xd.double(), 8)
     with pytest.raises(ValueError):
         iqa_tiles(xd.t(), xd, 8)
+
+
+# 2048/256 split 64 ways: 64 tile groups x 64 parts x 16 B = 64 KiB of
+# partials, more than the 4 KiB a 512/512 launch needs.
+GROW_CFG = dict(vec=4, waves=1, unroll=4, seg=64, rp=1, ksplit=64)
+
+
+def test_graph_replays_with_split_workspace_growth():
+    """A captured split-shape launch stays correct across replays even after a
+    larger shape grows the stream's workspace (the old buffer is kept), with
+    eager work between the replays."""
+    from paper_2501_10653_amd import prepare
+    rng = np.random.default_rng(21)
+    x, y = synth.random_pair(512, rng, neg_frac=0.3, scale=1.0)
+    xd, yd = to_dev(x), to_dev(y)
+    cfg = split_cfg(512, 512, None)
+    s = torch.cuda.Stream()
+    prepare(512, 512, cfg, stream=s)
+    out = {"lisi": torch.empty(1, 1, device="cuda"), "auglisi": torch.empty(1, 1, device="cuda")}
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        iqa_tiles(xd, yd, 512, out=out, cfg=cfg, stream=s)
+    ora = oracle_for(x, y, 512)
+    x2, y2 = synth.random_pair(2048, rng, neg_frac=0.3, scale=1.0)
+    big = (to_dev(x2), to_dev(y2))
+    for rep in range(3):
+        out["lisi"].fill_(-1.0)
+        out["auglisi"].fill_(-1.0)
+        with torch.cuda.stream(s):
+            g.replay()
+            # eager work on the same stream, growing the workspace on the first pass
+            iqa_tiles(big[0], big[1], 256, cfg=GROW_CFG, stream=s)
+        torch.cuda.synchronize()
+        from paper_2501_10653_amd.iqa import TileResult
+        assert_parity(TileResult(out["lisi"], out["auglisi"], None), ora, what=f"replay {rep}")
+
+
+def test_single_pair_graph_replays_equal_eager(paper_pair):
+    _, _, xd, yd = paper_pair
+    eager = fused(xd, yd, 64)
+    s = torch.cuda.Stream()
+    out = {"lisi": torch.empty(32, 32, device="cuda"), "auglisi": torch.empty(32, 32, device="cuda")}
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        iqa_tiles(xd, yd, 64, out=out, stream=s)
+    for rep in range(3):
+        out["lisi"].zero_()
+        out["auglisi"].zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        assert same(out["lisi"], eager.lisi) and same(out["auglisi"], eager.auglisi), rep
