@@ -387,6 +387,7 @@ def main(argv=None) -> int:
 
     gpu_lisi = lisi.cpu().numpy()
     gpu_aug = aug.cpu().numpy()
+    reference = same_size_read(torch, dev, bytes_pair, pool, stream, read_ceiling, K)
 
     extras = {}
     if args.extras:
@@ -425,6 +426,8 @@ def main(argv=None) -> int:
         "hbm_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
         "wall_s_timed": round(wall, 4),
         "roofline": roofline,
+        "reference_read": {**reference,
+                           "kernel_frac_of_plain_read": round(gbs / reference["gbs"], 4)},
     }
     if extras:
         line["extras"] = extras
@@ -440,6 +443,34 @@ def main(argv=None) -> int:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
     return 0
+
+
+def same_size_read(torch, dev, nbytes: int, pool: int, stream, read_ceiling, K: int) -> dict:
+    """A plain float4 read of the same number of bytes per launch, over a pool
+    of distinct buffers and timed the same way (K launches in one graph):
+    what a launch of this size can reach on this GPU."""
+    bufs = [torch.empty(nbytes // 4, device=dev) for _ in range(pool)]
+    for b in bufs:
+        b.fill_(1.0)
+    out = torch.empty(2048, device=dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for i in range(K):
+            read_ceiling(bufs[i % pool], out, stream=stream)
+    with torch.cuda.stream(stream):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / K * 1e3
+    del g, bufs
+    torch.cuda.empty_cache()
+    return {"us_per_launch": round(us, 3), "gbs": round(nbytes / us / 1e3, 1),
+            "workgroups": 2048}
 
 
 def run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling, lisi_tiles,

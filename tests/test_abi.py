@@ -8,6 +8,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -215,3 +216,18 @@ def test_header_is_plain_c_and_links(tmp_path):
     mirrors = [LaunchCfg, _lib.IqaPair, _lib.ServerOpts, _lib.Request, _lib.Completion,
                _lib.ServerStats]
     assert sizes == [ctypes.sizeof(m) for m in mirrors]
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No CPU fallback: without the built library every entry point raises."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2501_10653_amd import _lib\n"
+            "_lib.LIB_PATH = %r\n"
+            "try:\n"
+            "    _lib.load()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(1)\n") % (ROOT, str(tmp_path / "missing.so"))
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert res.returncode == 0 and "not built" in res.stdout
