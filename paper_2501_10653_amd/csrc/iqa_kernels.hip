@@ -63,6 +63,8 @@ struct KArgs {
     int32_t rows_wave;   // tile rows per wave slice: NT / (waves * ks)
     int32_t lpt;         // column groups per tile row: NT / vec
     int32_t cpl;         // column chunks per lane: ceil(lpt / seg)
+    uint32_t ngx_m;      // division multipliers for ngx and ks (see udiv)
+    uint32_t ks_m;
     float D, C1, C2, C;
     float *lisi;
     float *aug;
@@ -303,12 +305,24 @@ __device__ __forceinline__ Acc acc_of(const Sum4 &s) {
 // one offset class that b % 8 would give it.
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ int xcd_remap(int b, int grid) {
-    const int xcd = b % kXcds;
-    const int local = b / kXcds;
-    const int full = grid / kXcds;
-    const int rem = grid % kXcds;
-    return xcd * full + (xcd < rem ? xcd : rem) + local;
+__device__ __forceinline__ int xcd_remap(uint32_t b, uint32_t grid) {
+    const uint32_t xcd = b % kXcds;
+    const uint32_t local = b / kXcds;
+    const uint32_t full = grid / kXcds;
+    const uint32_t rem = grid % kXcds;
+    return (int)(xcd * full + (xcd < rem ? xcd : rem) + local);
+}
+
+// Division by a divisor d fixed for the launch (1 <= d < 2^31), for numerators
+// 0 <= n < 2^31, without the ~30-instruction integer division sequence: with
+// l = ceil(log2 d) and m = floor(2^(31+l) / d) + 1 (< 2^32, computed on the
+// host by div_magic), n / d = (n * m) >> (31 + l) exactly (Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994,
+// Theorem 4.2 with 31-bit numerators).  Block indices are wave-uniform, so
+// this runs on the scalar unit ahead of the first load.
+__device__ __forceinline__ int udiv(int n, uint32_t m, int d) {
+    const uint32_t l = d > 1 ? 32u - (uint32_t)__clz((uint32_t)d - 1u) : 0u;
+    return (int)(((uint64_t)(uint32_t)n * m) >> (31u + l));
 }
 
 // ---------------------------------------------------------------------------
@@ -325,14 +339,15 @@ template <int VEC, int U, int MODE, bool WIDE>
 __device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int slice, int lane) {
     using V = typename VecT<VEC>::T;
     const int seg = 1 << a.log_seg;
-    const int rp = 1 << (a.log_grp - a.log_seg);
+    const int log_rp = a.log_grp - a.log_seg;
+    const int rp = 1 << log_rp;
     const int l = lane & (seg - 1);
     const int k = (lane >> a.log_seg) & (rp - 1);
     const int j = lane >> a.log_grp;
     const int tx = txg * a.ht + j;
 
-    int M = 0;   // rows of the tile this lane reduces
-    if (tx < a.ns && k < a.rows_wave) M = (a.rows_wave - k + rp - 1) / rp;
+    int M = 0;   // rows of the tile this lane reduces: ceil((rows_wave - k) / rp)
+    if (tx < a.ns && k < a.rows_wave) M = (a.rows_wave - k + rp - 1) >> log_rp;
     const int64_t col0 = (int64_t)tx * a.NT;
     // First row of the slice: uniform across the wave, so the image pointers
     // below live in scalar registers.
@@ -449,9 +464,9 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int grp = bid / a.ks;
+    const int grp = udiv(bid, a.ks_m, a.ks);
     const int part = bid - grp * a.ks;
-    const int ty = grp / a.ngx;
+    const int ty = udiv(grp, a.ngx_m, a.ngx);
     const int txg = grp - ty * a.ngx;
     const int j = lane >> a.log_grp;
     const int tx = txg * a.ht + j;
@@ -532,7 +547,7 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel(const BatchD
         const int pi = __builtin_amdgcn_readfirstlane(lo);
         const KArgs a = descs[pi].a;
         const int grp = (int)(u - descs[pi].unit_begin);
-        const int ty = grp / a.ngx;
+        const int ty = udiv(grp, a.ngx_m, a.ngx);
         const int txg = grp - ty * a.ngx;
         const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, 0, lane)
                                  : slice_sums<4, U, kBoth, false>(a, ty, txg, 0, lane);
@@ -732,6 +747,12 @@ int ilog2(int64_t v) {
     return r;
 }
 int64_t next_pow2(int64_t v) { return int64_t(1) << ilog2(v); }
+
+// Multiplier m = floor(2^(31 + ceil(log2 d)) / d) + 1 for udiv (1 <= d < 2^31).
+uint32_t div_magic(int64_t d) {
+    const int l = ilog2(d);
+    return (uint32_t)(((uint64_t)1 << (31 + l)) / (uint64_t)d + 1);
+}
 
 bool param_ok(float v) {
     return std::isfinite(v) && v > 0.f && std::fpclassify(v) == FP_NORMAL;
@@ -935,6 +956,8 @@ void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, 
     a.rows_wave = (int32_t)(NT / ((int64_t)c.waves * c.ksplit));
     a.lpt = g.lpt;
     a.cpl = g.cpl;
+    a.ngx_m = div_magic(g.ngx);
+    a.ks_m = div_magic(c.ksplit);
     a.D = D;
     a.C1 = C1;
     a.C2 = C2;
