@@ -49,8 +49,9 @@ def parse_args(argv=None):
                     help="wall time of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of a graph")
-    ap.add_argument("--extras", action="store_true",
-                    help="also time the read ceiling and the two separate kernels")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements of the default run (the 2 GiB read "
+                         "ceiling, the two separate kernels, the same-shape batch)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: a few eager launches plus a 256 MiB copy of known size")
     ap.add_argument("--serve-rate", type=float, default=10000.0,
@@ -128,6 +129,41 @@ def cpu_baseline(x, y, NT, seconds: float, bytes_pair: int, n_tiles: int,
                                     "pass_1e-5": bool(lisi_rel.max() <= 1e-5
                                                       and aug_err.max() <= 1e-5)},
     }
+
+
+def cpu_single_thread(x, y, NT, seconds: float, bytes_pair: int) -> dict:
+    """The same oracle on one OpenMP thread (per-tile summation order is the
+    same, so its results are bitwise those of the threaded run)."""
+    from oracle import oracle
+    c = oracle.f32const(1e-6)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        used = oracle.num_threads()
+        oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": round(bytes_pair * reps / el / 1e9, 4), "unit": "GB/s", "cores": used,
+            "ms_per_pair": round(el / reps * 1e3, 3),
+            "sample": f"the same pair, {reps} repetitions in {el:.1f} s"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 class ServingWorld:
@@ -217,6 +253,8 @@ def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
         x, y = proto[(sp.N, 1 if sp.n_drop else 0)]
         pairs.append((x.clone(), y.clone(), sp.NT))
     del proto
+    from paper_2501_10653_amd.tune import evict_infinity_cache
+    evict_infinity_cache(torch, dev)
     total = sum(8 * p[0].shape[0] ** 2 for p in pairs)
     s = torch.cuda.Stream(dev)
 
@@ -279,6 +317,7 @@ def main(argv=None) -> int:
     import torch
     from paper_2501_10653_amd import default_cfg, iqa_tiles, synth
     from paper_2501_10653_amd.iqa import auglisi_tiles, lisi_tiles, read_ceiling
+    from paper_2501_10653_amd.tune import device_copies, evict_infinity_cache
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no HIP device visible"}))
@@ -318,11 +357,9 @@ def main(argv=None) -> int:
     x, y, _ = synth.make_pair(spec)
     bytes_pair = 8 * N * N
     pool = max(2, int(math.ceil(args.pool_bytes / bytes_pair)))
-    xs = [torch.from_numpy(x).to(dev) for _ in range(1)]
-    ys = [torch.from_numpy(y).to(dev) for _ in range(1)]
-    for _ in range(pool - 1):
-        xs.append(xs[0].clone())
-        ys.append(ys[0].clone())
+    xs = device_copies(torch, dev, x, pool)
+    ys = device_copies(torch, dev, y, pool)
+    evict_infinity_cache(torch, dev)
     lisi = torch.empty(ns, ns, device=dev)
     aug = torch.empty(ns, ns, device=dev)
     out = {"lisi": lisi, "auglisi": aug}
@@ -389,10 +426,11 @@ def main(argv=None) -> int:
     gpu_aug = aug.cpu().numpy()
     reference = same_size_read(torch, dev, bytes_pair, pool, stream, read_ceiling, K)
 
-    extras = {}
-    if args.extras:
+    extras, batched = {}, None
+    if not args.no_extras:
         extras = run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling,
                             lisi_tiles, auglisi_tiles, iqa_tiles, cfg, bytes_pair)
+        batched = run_same_shape_batch(torch, xs, ys, NT, stream, bytes_pair, gbs)
 
     traffic = traffic_record(N, NT, cfg)
     roofline = {
@@ -431,6 +469,8 @@ def main(argv=None) -> int:
     }
     if extras:
         line["extras"] = extras
+    if batched:
+        line["batched"] = batched
     if args.serve_rate > 0 and args.workload == "paper":
         del xs, ys
         torch.cuda.empty_cache()
@@ -439,6 +479,9 @@ def main(argv=None) -> int:
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, NT, args.cpu_seconds, bytes_pair, ns * ns,
                                             gpu_lisi, gpu_aug)
+        line["cpu_baseline"]["cpu_model"] = cpu_model()
+        line["cpu_baseline"]["single_thread"] = cpu_single_thread(
+            x, y, NT, min(5.0, args.cpu_seconds), bytes_pair)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
@@ -498,6 +541,8 @@ def run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling, lisi_tiles
     ns = N // NT
     lo = torch.empty(ns, ns, device=dev)
     ao = torch.empty(ns, ns, device=dev)
+    from paper_2501_10653_amd.tune import evict_infinity_cache
+    evict_infinity_cache(torch, dev)
     K = 400
     for name, fn in (("lisi_only", lambda i: lisi_tiles(xs[i % pool], ys[i % pool], NT, out=lo,
                                                          stream=stream)),
@@ -523,6 +568,39 @@ def run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling, lisi_tiles
         ex[f"{name}_gbs"] = round(bytes_pair / (ms * 1e-3) / 1e9, 1)
     ex["separate_total_us"] = round(ex["lisi_only_us"] + ex["auglisi_only_us"], 3)
     return ex
+
+
+def run_same_shape_batch(torch, xs, ys, NT, stream, bytes_pair, single_gbs, reps: int = 20) -> dict:
+    """Every pair of the pool in one persistent batch launch (the ragged-batch
+    kernel with all pairs of one shape), `reps` launches in one graph: the
+    throughput of the same pairs when they come as a batch rather than one
+    launch each, next to the single-launch value."""
+    from paper_2501_10653_amd.batch import Batch
+    from paper_2501_10653_amd.tune import evict_infinity_cache
+    b = Batch([(x, y, NT) for x, y in zip(xs, ys)])
+    evict_infinity_cache(torch, xs[0].device)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(reps):
+            b.run(stream=stream)
+    with torch.cuda.stream(stream):
+        g.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    with torch.cuda.stream(stream):
+        g.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    gbs = len(xs) * bytes_pair / (ms * 1e-3) / 1e9
+    out = {"pairs_per_launch": len(xs), "launches": reps, "waves": b.waves,
+           "us_per_launch": round(ms * 1e3, 2),
+           "us_per_pair": round(ms * 1e3 / len(xs), 3),
+           "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+           "vs_single_launch": round(gbs / single_gbs, 3)}
+    del g, b
+    return out
 
 
 if __name__ == "__main__":

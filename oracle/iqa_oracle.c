@@ -153,6 +153,18 @@ int oracle_merge_tiles(const double *lisi_c, const double *aug_c, const double *
     return ORACLE_OK;
 }
 
+/* Threads for later calls (n >= 1); tiles are independent, so the count
+ * changes the wall time only, never a result bit.  No effect without OpenMP. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads a parallel region of this library will use
  * (1 when built without OpenMP). */
 int oracle_num_threads(void)

@@ -56,6 +56,8 @@ def _load() -> ctypes.CDLL:
         lib.oracle_merge_tiles.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -125,3 +127,8 @@ def merge_tiles(lisi: np.ndarray, aug: np.ndarray, sums: np.ndarray, f: int,
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for later calls (results are bitwise the same)."""
+    _load().oracle_set_num_threads(int(n))

@@ -91,15 +91,33 @@ class _Timer:
         return float(np.median(ts))
 
 
+def evict_infinity_cache(torch, dev, nbytes: int = 512 << 20, passes: int = 4) -> None:
+    """Age out whatever the 256 MB Infinity Cache holds: several passes of
+    ordinary loads over a scratch buffer twice its size, with nothing else
+    re-read in between.  (Data that was re-read often, such as the source of
+    many device-side clones, otherwise stays cached through single streaming
+    passes, and the tile kernels' non-temporal loads never displace it.)"""
+    buf = torch.ones(nbytes // 4, device=dev)
+    for _ in range(passes):
+        float(buf.sum())
+    del buf
+
+
+def device_copies(torch, dev, arr, count: int):
+    """`count` distinct device copies of a host array, each uploaded from the
+    host: no device buffer is re-read while the pool is built, so none of
+    them starts out resident in the Infinity Cache."""
+    host = torch.from_numpy(arr)
+    return [host.to(dev) for _ in range(count)]
+
+
 def _pool(torch, dev, N: int, NT: int, pool_bytes: float):
     from . import synth
     x, y, _ = synth.make_pair(synth.spec_sweep(N, NT))
     n = max(2, int(math.ceil(pool_bytes / (8 * N * N))))
-    xs = [torch.from_numpy(x).to(dev)]
-    ys = [torch.from_numpy(y).to(dev)]
-    for _ in range(n - 1):
-        xs.append(xs[0].clone())
-        ys.append(ys[0].clone())
+    xs = device_copies(torch, dev, x, n)
+    ys = device_copies(torch, dev, y, n)
+    evict_infinity_cache(torch, dev)
     return xs, ys
 
 
@@ -163,6 +181,7 @@ def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 102
     log_rows = []
     for NT in NTs:
         pairs = [(proto[N][0].clone(), proto[N][1].clone(), NT) for N in Ns for _ in range(copies)]
+        evict_infinity_cache(torch, dev)
         total = sum(8 * p[0].shape[0] ** 2 for p in pairs)
         res = []
         for cfg in candidates_batch(NT):
@@ -183,6 +202,7 @@ def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 102
     # persistent waves on the mixed batch
     mixed = [(proto[N][0].clone(), proto[N][1].clone(), NT) for N in Ns for NT in NTs
              for _ in range(max(1, copies // 2))]
+    evict_infinity_cache(torch, dev)
     total = sum(8 * p[0].shape[0] ** 2 for p in mixed)
     wres = []
     for w in waves_list:

@@ -305,3 +305,20 @@ def test_thread_count_does_not_change_bits():
         outs.append(json.loads(res.stdout.strip().splitlines()[-1]))
     assert outs[0][:2] == outs[1][:2]
     assert outs[0][2] == 1 and outs[1][2] == 4
+
+
+def test_set_num_threads_keeps_bits():
+    """Changing the thread count in-process leaves every result bit as is."""
+    rng = np.random.default_rng(5)
+    x, y = synth.random_pair(128, rng)
+    before = oracle.num_threads()
+    ref = oracle.iqa_tiles(x, y, 16, D32, C32, C32, C32)
+    try:
+        oracle.set_num_threads(1)
+        assert oracle.num_threads() == 1
+        one = oracle.iqa_tiles(x, y, 16, D32, C32, C32, C32)
+    finally:
+        oracle.set_num_threads(before)
+    assert oracle.num_threads() == before
+    for a, b in zip(ref, one):
+        assert a.tobytes() == b.tobytes()
