@@ -47,8 +47,6 @@ def test_paper_shape_2048_nt64():
 @pytest.mark.parametrize("N", [1024, 2048, 4096, 8192])
 @pytest.mark.parametrize("NT", [16, 32, 64, 128, 256])
 def test_sweep_cells(N, NT):
-    if N == 8192 and NT not in (16, 256):
-        pytest.skip("8192 checked at the smallest and largest tile only (runtime)")
     x, y, _ = synth.make_pair(synth.spec_sweep(N, NT))
     res = run_pair(x, y, NT)
     stats = assert_parity(res, oracle_for(x, y, NT), what=f"{N}/{NT}")
