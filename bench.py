@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "fused LISI+augLISI HBM GB/s (% peak) at 2048²/NT64; p99 request latency"
 HBM_PEAK_GBS = 8000.0       # MI355X published HBM3E bandwidth
+READ_BLOCKS = 1024          # workgroups of the same-size plain read (its fastest measured shape)
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_10653_amd", "csrc", "iqa_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -492,10 +493,12 @@ def same_size_read(torch, dev, nbytes: int, pool: int, stream, read_ceiling, K: 
     """A plain float4 read of the same number of bytes per launch, over a pool
     of distinct buffers and timed the same way (K launches in one graph):
     what a launch of this size can reach on this GPU."""
+    from paper_2501_10653_amd.tune import evict_infinity_cache
     bufs = [torch.empty(nbytes // 4, device=dev) for _ in range(pool)]
     for b in bufs:
         b.fill_(1.0)
-    out = torch.empty(2048, device=dev)
+    evict_infinity_cache(torch, dev)
+    out = torch.empty(READ_BLOCKS, device=dev)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
         for i in range(K):
@@ -513,7 +516,7 @@ def same_size_read(torch, dev, nbytes: int, pool: int, stream, read_ceiling, K: 
     del g, bufs
     torch.cuda.empty_cache()
     return {"us_per_launch": round(us, 3), "gbs": round(nbytes / us / 1e3, 1),
-            "workgroups": 2048}
+            "workgroups": READ_BLOCKS, "loads": "non-temporal float4"}
 
 
 def run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling, lisi_tiles,

@@ -353,10 +353,11 @@ iqa_status iqa_server_destroy(iqa_server *sv);
 /* ------------------------------------------------------------------------ */
 
 /* Streaming-read reference kernel, for measurement only: `blocks`
- * workgroups each sum a contiguous share of the n floats at `buf` (device,
- * 16-byte aligned, n % 4 == 0) and write one float each to `out` (device,
- * `blocks` floats).  Its bandwidth is the attainable HBM read rate that the
- * tile kernels are compared with; the sums themselves carry no meaning. */
+ * workgroups of 256 threads each sum a contiguous share of the n floats at
+ * `buf` (device, 16-byte aligned, n % 4 == 0) with the same non-temporal
+ * 16-byte loads as the tile kernels, and write one float each to `out`
+ * (device, `blocks` floats).  Its bandwidth is the attainable HBM read rate
+ * that the tile kernels are compared with; the sums carry no meaning. */
 iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blocks,
                             void *stream);
 
