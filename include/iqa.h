@@ -247,6 +247,20 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
 iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
                              int64_t waves, void *stream);
 
+/* Largest batch iqa_tiles_batched_inline takes. */
+#define IQA_BATCH_INLINE_MAX 16
+
+/* The same launch for a small batch whose descriptors stay in host memory:
+ *   descs_host   host copy of the descriptors from iqa_batch_describe, for
+ *                1 <= count <= IQA_BATCH_INLINE_MAX pairs (else IQA_ERR_SHAPE).
+ * The descriptors travel by value in the kernel arguments, so no device table
+ * and no copy precede the launch (one enqueue instead of two), and the host
+ * buffer may be reused as soon as the call returns.  Results are bitwise
+ * those of iqa_tiles_batched on the same descriptors.  Captured into a HIP
+ * graph, the launch keeps the descriptors it was given. */
+iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count,
+                                    int64_t total_units, int64_t waves, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of snapshot-vs-reference requests            */
 /* ------------------------------------------------------------------------ */
@@ -256,7 +270,8 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
  * scheduler thread admits requests in arrival order while the bytes held by
  * admitted, unfinished requests stay within `hbm_budget_bytes` (a request
  * holds its snapshot, 4*N*N bytes, plus its output matrices), and packs all
- * admitted requests into one iqa_tiles_batched launch whenever one of
+ * admitted requests into one batched launch (iqa_tiles_batched_inline up to
+ * IQA_BATCH_INLINE_MAX requests, else iqa_tiles_batched) whenever one of
  * `streams` launch slots is free; a slot frees when its batch's completion
  * event fires.  Requests arriving while batches run join the next launch, so
  * batches overlap on the device.  A request's results are bitwise the same
@@ -272,6 +287,9 @@ typedef struct iqa_server_opts {
     int32_t streams;           /* launch slots = batches in flight, 1..16 */
     int32_t max_batch;         /* requests per launch, 1..2^20 */
     float D, C1, C2, C;        /* Eq. 1 / Eq. 2 constants for every request */
+    int64_t idle_spin_ns;      /* with nothing to do, keep polling this long after
+                                  the last work before sleeping (0..1e9; 0 sleeps
+                                  at once; polling occupies one CPU core) */
 } iqa_server_opts;
 
 typedef struct iqa_request {

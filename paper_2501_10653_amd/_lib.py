@@ -51,7 +51,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("host_arena_bytes", ctypes.c_int64),
                 ("waves", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("D", ctypes.c_float), ("C1", ctypes.c_float),
-                ("C2", ctypes.c_float), ("C", ctypes.c_float)]
+                ("C2", ctypes.c_float), ("C", ctypes.c_float), ("idle_spin_ns", ctypes.c_int64)]
 
 
 class Request(ctypes.Structure):
@@ -83,6 +83,7 @@ class ServerStats(ctypes.Structure):
 
 
 BATCH_DESC_BYTES = 128
+BATCH_INLINE_MAX = 16
 TUNE_SINGLE = 0
 TUNE_BATCH = 1
 
@@ -137,6 +138,7 @@ def load() -> ctypes.CDLL:
         "iqa_batch_describe": ([ctypes.POINTER(IqaPair), i64, vp, ctypes.POINTER(i64)],
                                ctypes.c_int),
         "iqa_tiles_batched": ([vp, i64, i64, i64, vp], ctypes.c_int),
+        "iqa_tiles_batched_inline": ([vp, i64, i64, i64, vp], ctypes.c_int),
         "iqa_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)], ctypes.c_int),
         "iqa_server_create_dry": ([ctypes.POINTER(ServerOpts), i64, ctypes.c_double,
                                    ctypes.POINTER(vp)], ctypes.c_int),

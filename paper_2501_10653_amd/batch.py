@@ -46,7 +46,8 @@ class Batch:
 
     def __init__(self, pairs: Sequence, *, C1: float = C_DEFAULT, C2: float = C_DEFAULT,
                  C: float = C_DEFAULT, D: Optional[float] = None, sums: bool = False,
-                 waves: Optional[int] = None, device: Optional[torch.device] = None):
+                 waves: Optional[int] = None, device: Optional[torch.device] = None,
+                 inline: Optional[bool] = None):
         if len(pairs) == 0:
             raise ValueError("empty batch")
         if D is None:
@@ -72,6 +73,12 @@ class Batch:
         self.count = len(batched)
         self.units = 0
         self.descs = None
+        self.descs_host = None
+        # Up to BATCH_INLINE_MAX pairs travel in the kernel arguments (no
+        # device table); `inline` forces either form.
+        self.inline = (self.count <= _lib.BATCH_INLINE_MAX) if inline is None else bool(inline)
+        if self.inline and self.count > _lib.BATCH_INLINE_MAX:
+            raise ValueError(f"inline batches hold at most {_lib.BATCH_INLINE_MAX} pairs")
         if batched:
             arr = (IqaPair * len(batched))()
             for k, i in enumerate(batched):
@@ -85,15 +92,24 @@ class Batch:
             _lib.check(_lib.load().iqa_batch_describe(arr, len(batched), host.ctypes.data,
                                                       ctypes.byref(units)), "iqa_batch_describe")
             self.units = int(units.value)
-            self.descs = torch.from_numpy(host).to(self.device)   # device copy, 256-B aligned
+            if self.inline:
+                self.descs_host = host
+            else:
+                self.descs = torch.from_numpy(host).to(self.device)   # device copy, 256-B aligned
 
     def run(self, stream=None) -> None:
         """Enqueue the batch: one persistent launch over every pair with
-        N_T % 4 == 0 and 16-byte aligned images, and a single-pair launch for
-        each of the others, all on the same stream."""
+        N_T % 4 == 0 and 16-byte aligned images (descriptors in the kernel
+        arguments or in a device table), and a single-pair launch for each of
+        the others, all on the same stream."""
         from .iqa import iqa_tiles
         with torch.cuda.device(self.device):
-            if self.descs is not None:
+            if self.descs_host is not None:
+                st = _lib.load().iqa_tiles_batched_inline(self.descs_host.ctypes.data, self.count,
+                                                          self.units, self.waves,
+                                                          _stream_handle(self.device, stream))
+                _lib.check(st, "iqa_tiles_batched_inline")
+            elif self.descs is not None:
                 st = _lib.load().iqa_tiles_batched(self.descs.data_ptr(), self.count, self.units,
                                                    self.waves,
                                                    _stream_handle(self.device, stream))

@@ -542,8 +542,7 @@ static_assert(sizeof(BatchDesc) <= IQA_BATCH_DESC_BYTES, "batch descriptor size"
 constexpr int kBatchWaves = 4;   // independent waves per workgroup
 
 template <int U>
-__global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel(const BatchDesc *descs,
-                                                                    int count, int64_t units) {
+__device__ __forceinline__ void batch_body(const BatchDesc *descs, int count, int64_t units) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t nw = (int64_t)gridDim.x * kBatchWaves;
@@ -566,6 +565,27 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel(const BatchD
         if ((lane & ((1 << a.log_grp) - 1)) == 0 && tx < a.ns)
             finalize<kBoth>(a, (int64_t)ty * a.ns + tx, acc_of(s));
     }
+}
+
+// The descriptor table in device memory (any number of pairs).
+template <int U>
+__global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel(const BatchDesc *descs,
+                                                                    int count, int64_t units) {
+    batch_body<U>(descs, count, units);
+}
+
+// Up to IQA_BATCH_INLINE_MAX descriptors passed by value in the kernel
+// arguments: no table to copy to the device before the launch.  The waves
+// read the descriptors straight from the kernel-argument segment.
+struct InlineDescs {
+    BatchDesc d[IQA_BATCH_INLINE_MAX];
+    int64_t units;
+    int32_t count;
+};
+
+template <int U>
+__global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel_inline(InlineDescs in) {
+    batch_body<U>(in.d, in.count, in.units);
 }
 
 // Split tiles: one thread per tile adds the ks parts' partial sums in part
@@ -1194,6 +1214,29 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
     return IQA_OK;
 }
 
+iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count, int64_t total_units,
+                                    int64_t waves, void *stream) {
+    if (!descs_host) return IQA_ERR_NULL;
+    if (count < 1 || count > IQA_BATCH_INLINE_MAX || total_units < 1) return IQA_ERR_SHAPE;
+    if (waves < kBatchWaves || waves % kBatchWaves != 0 || waves / kBatchWaves > INT_MAX)
+        return IQA_ERR_CONFIG;
+    InlineDescs in;
+    std::memset(&in, 0, sizeof(in));
+    std::memcpy(in.d, descs_host, (size_t)count * sizeof(BatchDesc));
+    in.units = total_units;
+    in.count = (int32_t)count;
+    const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
+                                             (total_units + kBatchWaves - 1) / kBatchWaves);
+    hipLaunchKernelGGL(batch_kernel_inline<kBatchUnroll>, dim3((unsigned)blocks),
+                       dim3(kBatchWaves * kWave), 0, static_cast<hipStream_t>(stream), in);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return IQA_ERR_HIP;
+    }
+    return IQA_OK;
+}
+
 iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D, float C2,
                            float C, float *lisi, float *auglisi, float *sums_out, void *stream) {
     if (!sums_in) return IQA_ERR_NULL;
@@ -1250,6 +1293,6 @@ const char *iqa_status_str(int status) {
 
 int iqa_last_hip_error(void) { return g_last_hip_error; }
 
-int iqa_version(void) { return 200; }
+int iqa_version(void) { return 300; }
 
 }  // extern "C"

@@ -144,7 +144,10 @@ bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
     int64_t units = 0;
     if (ok && iqa_batch_describe(pairs.data(), (int64_t)pairs.size(), s.desc_host, &units) != IQA_OK)
         ok = false;
-    if (ok) {
+    // Small batches carry their descriptors in the kernel arguments (one
+    // enqueue); larger ones copy the table to the slot's device buffer first.
+    const bool inl = pairs.size() <= (size_t)IQA_BATCH_INLINE_MAX;
+    if (ok && !inl) {
         hipError_t e = hipMemcpyAsync(s.desc_dev, s.desc_host,
                                       pairs.size() * IQA_BATCH_DESC_BYTES,
                                       hipMemcpyHostToDevice, s.stream);
@@ -153,10 +156,16 @@ bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
             ok = false;
         }
     }
-    if (ok && iqa_tiles_batched(s.desc_dev, (int64_t)pairs.size(), units, opts.waves,
-                                s.stream) != IQA_OK) {
-        last_hip_error = iqa_last_hip_error();
-        ok = false;
+    if (ok) {
+        const iqa_status st =
+            inl ? iqa_tiles_batched_inline(s.desc_host, (int64_t)pairs.size(), units, opts.waves,
+                                           s.stream)
+                : iqa_tiles_batched(s.desc_dev, (int64_t)pairs.size(), units, opts.waves,
+                                    s.stream);
+        if (st != IQA_OK) {
+            last_hip_error = iqa_last_hip_error();
+            ok = false;
+        }
     }
     if (ok) {
         hipError_t e = hipEventRecord(s.done, s.stream);
@@ -196,6 +205,7 @@ void iqa_server::run() {
     if (!dry) (void)hipSetDevice(device);
     const int64_t budget = opts.hbm_budget_bytes;
     std::vector<Pending> batch;
+    int64_t last_active = now_ns();
     while (true) {
         bool idle = true;
         {
@@ -205,6 +215,7 @@ void iqa_server::run() {
                 for (const Slot &s : slots) any_busy |= s.busy;
                 if (!any_busy) break;
             }
+            if (!intake.empty()) idle = false;
             while (!intake.empty()) {
                 pending.push_back(intake.front());
                 intake.pop_front();
@@ -268,13 +279,18 @@ void iqa_server::run() {
             }
             idle = false;
         }
-        if (idle) {
+        if (!idle) {
+            last_active = now_ns();
+        } else {
             std::unique_lock<std::mutex> lock(mu);
             bool any_busy = false;
             for (const Slot &s : slots) any_busy |= s.busy;
-            if (any_busy) {
+            if (any_busy || now_ns() - last_active < opts.idle_spin_ns) {
+                // Poll the events (or, for idle_spin_ns after the last work,
+                // the intake) without sleeping: a wake-up from the condition
+                // variable costs tens of microseconds.
                 lock.unlock();
-                std::this_thread::yield();   // poll the events without sleeping
+                std::this_thread::yield();
             } else if (intake.empty() && !stop) {
                 cv.wait_for(lock, std::chrono::milliseconds(1));
             }
@@ -290,6 +306,7 @@ static iqa_status check_opts(const iqa_server_opts *opts) {
         opts->host_arena_bytes < 0)
         return IQA_ERR_CONFIG;
     if (opts->waves != 0 && (opts->waves < 4 || opts->waves % 4 != 0)) return IQA_ERR_CONFIG;
+    if (opts->idle_spin_ns < 0 || opts->idle_spin_ns > 1000000000) return IQA_ERR_CONFIG;
     return IQA_OK;
 }
 

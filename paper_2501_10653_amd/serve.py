@@ -46,11 +46,13 @@ class ServedRequest:
 class Server:
     def __init__(self, budget_bytes: int, *, streams: int = 2, max_batch: int = 512,
                  waves: int = 0, host_arena_bytes: int = 0, C1: float = C_DEFAULT,
-                 C2: float = C_DEFAULT, C: float = C_DEFAULT, D: Optional[float] = None):
+                 C2: float = C_DEFAULT, C: float = C_DEFAULT, D: Optional[float] = None,
+                 idle_spin_us: float = 1000.0):
         if D is None:
             D = default_D(C1)
         self.opts = ServerOpts(int(budget_bytes), int(host_arena_bytes), int(waves),
-                               int(streams), int(max_batch), D, C1, C2, C)
+                               int(streams), int(max_batch), D, C1, C2, C,
+                               int(idle_spin_us * 1000))
         self._lib = _lib.load()
         h = ctypes.c_void_p()
         _lib.check(self._lib.iqa_server_create(ctypes.byref(self.opts), ctypes.byref(h)),

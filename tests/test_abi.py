@@ -161,6 +161,22 @@ def test_batch_launch_validation():
     assert lib.iqa_tiles_batched(FAKE + 8, 1, 1, 2048, None) == ALIGN
 
 
+def test_inline_batch_launch_validation():
+    """Descriptors by value: at most IQA_BATCH_INLINE_MAX pairs, checked
+    before anything is copied or launched."""
+    import numpy as np
+    lib = _lib.load()
+    host = np.zeros(17 * _lib.BATCH_DESC_BYTES, np.uint8)
+    p = host.ctypes.data
+    assert lib.iqa_tiles_batched_inline(None, 1, 1, 2048, None) == NULL
+    assert lib.iqa_tiles_batched_inline(p, 0, 1, 2048, None) == SHAPE
+    assert lib.iqa_tiles_batched_inline(p, _lib.BATCH_INLINE_MAX + 1, 1, 2048, None) == SHAPE
+    assert lib.iqa_tiles_batched_inline(p, 1, 0, 2048, None) == SHAPE
+    assert lib.iqa_tiles_batched_inline(p, 1, 1, 2046, None) == CONFIG
+    header = open(os.path.join(ROOT, "include", "iqa.h")).read()
+    assert f"#define IQA_BATCH_INLINE_MAX {_lib.BATCH_INLINE_MAX}" in header
+
+
 def test_tune_registry():
     lib = _lib.load()
     lib.iqa_tune_clear()
@@ -190,7 +206,8 @@ def test_tune_registry():
 
 
 @pytest.mark.parametrize("over", [dict(streams=0), dict(streams=17), dict(max_batch=0),
-                                  dict(hbm_budget_bytes=0), dict(waves=6), dict(host_arena_bytes=-1)])
+                                  dict(hbm_budget_bytes=0), dict(waves=6), dict(host_arena_bytes=-1),
+                                  dict(idle_spin_ns=-1), dict(idle_spin_ns=2_000_000_000)])
 def test_server_options_validated_before_any_gpu_call(over):
     kw = dict(hbm_budget_bytes=1 << 30, host_arena_bytes=0, waves=0, streams=2, max_batch=64,
               D=C6 / 2, C1=C6, C2=C6, C=C6)

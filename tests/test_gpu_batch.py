@@ -89,6 +89,37 @@ def test_graph_replays_equal_eager(ragged):
             assert same(l0, r.lisi) and same(a0, r.auglisi), rep
 
 
+def test_inline_descriptors_equal_device_table(ragged):
+    """Up to IQA_BATCH_INLINE_MAX pairs with their descriptors in the kernel
+    arguments: bitwise the launch from a device table, eager and replayed."""
+    host, dev = ragged
+    sub = [p for p in dev if p[2] % 4 == 0][:16]
+    assert len(sub) == 16
+    table = Batch(sub, sums=True, inline=False)
+    inl = Batch(sub, sums=True)
+    assert inl.inline and inl.descs is None and not table.inline
+    s = torch.cuda.Stream()
+    table.run(stream=s)
+    inl.run(stream=s)
+    torch.cuda.synchronize()
+    for r0, r1 in zip(table.results, inl.results):
+        assert same(r0.lisi, r1.lisi) and same(r0.auglisi, r1.auglisi) and same(r0.sums, r1.sums)
+    eager = [(r.lisi.clone(), r.auglisi.clone()) for r in inl.results]
+    g = inl.capture(s)
+    for rep in range(3):
+        for r in inl.results:
+            r.lisi.fill_(-1.0)
+            r.auglisi.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        for (l0, a0), r in zip(eager, inl.results):
+            assert same(l0, r.lisi) and same(a0, r.auglisi), rep
+    with pytest.raises(ValueError):
+        Batch(dev[:17] if len(dev) >= 17 else dev * 2, inline=True)
+
+
 def test_paper_recipe_pairs_in_a_batch():
     """Pairs built like the ragged-batch workload (sources removed in some,
     noise-only changes in the others) at mixed sizes up to 4096."""
