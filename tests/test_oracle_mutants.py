@@ -35,6 +35,14 @@ MUTANTS = {
     "merge_no_n_minus_1": ("(num_a - (n - 1.0) * C)", "(num_a)"),
     "merge_n_for_n_minus_1": ("(num_a - (n - 1.0) * C)", "(num_a - n * C)"),
     "merge_C_for_C2": ("num_l += lisi_c[t] * (fmax(sx, sy) + C2);", "num_l += lisi_c[t] * (fmax(sx, sy) + C);"),
+    "clamp_only_x": ("const double yi = clamp_negative(y[i]);", "const double yi = (double)y[i];"),
+    "diff_for_sum": ("const double sum_abs = fabs(xi + yi);", "const double sum_abs = fabs(xi - yi);"),
+    "Sy_from_x": ("Sy += yi;", "Sy += xi;"),
+    "aug_sign": ("auglisi[t] = 1.0 - P / (Sx + Sy + C);", "auglisi[t] = 1.0 + P / (Sx + Sy + C);"),
+    "merge_min_for_max": ("num_l += lisi_c[t] * (fmax(sx, sy) + C2);", "num_l += lisi_c[t] * (fmin(sx, sy) + C2);"),
+    "merge_weight_without_C": ("num_a += aug_c[t] * (sx + sy + C);", "num_a += aug_c[t] * (sx + sy);"),
+    "merge_A_from_P": ("A += sums_c[4 * t + 0];", "A += sums_c[4 * t + 1];"),
+    "merge_parent_sum_for_max": ("lisi_p[p] = num_l / (fmax(Sx, Sy) + C2);", "lisi_p[p] = num_l / (Sx + Sy + C2);"),
 }
 
 
