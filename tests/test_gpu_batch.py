@@ -14,8 +14,11 @@ from tests.gpu_util import assert_parity, oracle_for, requires_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
+# N_T 512 and 1024 take the kernel's wide path (a tile row wider than one
+# 64-lane segment); the rest the narrow one.
 SHAPES = [(64, 16), (128, 32), (256, 64), (512, 128), (1024, 32), (1024, 64), (512, 256),
-          (2048, 128), (96, 48), (300, 12), (1000, 20), (768, 256), (128, 128), (4096, 64)]
+          (2048, 128), (96, 48), (300, 12), (1000, 20), (768, 256), (128, 128), (4096, 64),
+          (1024, 512), (2048, 1024)]
 
 
 def same(a, b):
