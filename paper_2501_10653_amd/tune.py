@@ -92,11 +92,8 @@ class _Timer:
 
 
 def evict_infinity_cache(torch, dev, nbytes: int = 512 << 20, passes: int = 4) -> None:
-    """Age out whatever the 256 MB Infinity Cache holds: several passes of
-    ordinary loads over a scratch buffer twice its size, with nothing else
-    re-read in between.  (Data that was re-read often, such as the source of
-    many device-side clones, otherwise stays cached through single streaming
-    passes, and the tile kernels' non-temporal loads never displace it.)"""
+    """Age out whatever the 256 MB Infinity Cache holds before a timing:
+    several passes of ordinary loads over a scratch buffer twice its size."""
     buf = torch.ones(nbytes // 4, device=dev)
     for _ in range(passes):
         float(buf.sum())
@@ -105,8 +102,7 @@ def evict_infinity_cache(torch, dev, nbytes: int = 512 << 20, passes: int = 4) -
 
 def device_copies(torch, dev, arr, count: int):
     """`count` distinct device copies of a host array, each uploaded from the
-    host: no device buffer is re-read while the pool is built, so none of
-    them starts out resident in the Infinity Cache."""
+    host, so that no copy has been read on the device before a timing."""
     host = torch.from_numpy(arr)
     return [host.to(dev) for _ in range(count)]
 
