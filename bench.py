@@ -204,7 +204,7 @@ class ServingWorld:
 
 
 def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 30,
-                streams: int = 2, max_batch: int = 512, seed: int = 0,
+                streams: int = 4, max_batch: int = 512, seed: int = 0,
                 host: bool = False) -> dict:
     from paper_2501_10653_amd import synth
     from paper_2501_10653_amd.serve import Server, latency_summary

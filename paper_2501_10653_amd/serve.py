@@ -44,7 +44,7 @@ class ServedRequest:
 
 
 class Server:
-    def __init__(self, budget_bytes: int, *, streams: int = 2, max_batch: int = 512,
+    def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
                  waves: int = 0, host_arena_bytes: int = 0, C1: float = C_DEFAULT,
                  C2: float = C_DEFAULT, C: float = C_DEFAULT, D: Optional[float] = None,
                  idle_spin_us: float = 1000.0):
