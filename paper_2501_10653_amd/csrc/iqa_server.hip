@@ -375,10 +375,11 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
     if (!sv || !reqs) return IQA_ERR_NULL;
     if (count < 0) return IQA_ERR_SHAPE;
     const int64_t t = now_ns();
-    std::vector<Pending> ok;
-    ok.reserve(count);
+    // Validation reads the reference table, so it runs under the lock that
+    // add_reference takes: a first submit cannot race a late add_reference.
+    std::lock_guard<std::mutex> lock(sv->mu);
+    if (sv->stop) return IQA_ERR_CONFIG;
     int64_t rejected = 0;
-    std::vector<iqa_completion> bad;
     for (int64_t i = 0; i < count; ++i) {
         const iqa_request &r = reqs[i];
         int st = IQA_OK;
@@ -401,7 +402,7 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
             c.tag = r.tag;
             c.status = st;
             c.t_submit_ns = c.t_admit_ns = c.t_launch_ns = c.t_done_ns = t;
-            bad.push_back(c);
+            sv->done.push_back(c);
             ++rejected;
             continue;
         }
@@ -409,17 +410,11 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
         p.req = r;
         p.t_submit = t;
         p.cost = request_cost(*sv, r);
-        ok.push_back(p);
+        sv->intake.push_back(p);
     }
-    {
-        std::lock_guard<std::mutex> lock(sv->mu);
-        if (sv->stop) return IQA_ERR_CONFIG;
-        for (Pending &p : ok) sv->intake.push_back(p);
-        for (iqa_completion &c : bad) sv->done.push_back(c);
-        sv->submitted += count;
-        sv->completed += rejected;
-        sv->rejected += rejected;
-    }
+    sv->submitted += count;
+    sv->completed += rejected;
+    sv->rejected += rejected;
     sv->cv.notify_one();
     sv->cv_done.notify_all();
     return IQA_OK;
