@@ -22,6 +22,7 @@ import math
 import os
 import sys
 import time
+from typing import Optional
 
 import numpy as np
 
@@ -204,9 +205,15 @@ class ServingWorld:
 
 
 def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 30,
-                streams: int = 4, max_batch: int = 512, seed: int = 0,
+                streams: Optional[int] = None, max_batch: int = 512, seed: int = 0,
                 host: bool = False) -> dict:
+    """One open-loop serving run.  Launch slots default to 4 for device-resident
+    snapshots (more batches in flight cut the tail at high rates) and 2 for
+    host snapshots (their copies share one PCIe link, so more slots in flight
+    only stretch each batch)."""
     from paper_2501_10653_amd import synth
+    if streams is None:
+        streams = 2 if host else 4
     from paper_2501_10653_amd.serve import Server, latency_summary
     count = max(200, int(rate * seconds))
     arena = (2 << 30) if host else 0
