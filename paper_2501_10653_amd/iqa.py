@@ -62,6 +62,16 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _mark_used(stream, *tensors) -> None:
+    """Outputs allocated here on torch's current stream but written on another
+    torch stream: tell the caching allocator, so that their memory is not
+    handed out again before that stream has finished with it."""
+    if isinstance(stream, torch.cuda.Stream):
+        for t in tensors:
+            if t is not None:
+                t.record_stream(stream)
+
+
 def _out(shape, device, given: Optional[torch.Tensor], name: str) -> torch.Tensor:
     if given is None:
         return torch.empty(shape, dtype=torch.float32, device=device)
@@ -96,6 +106,8 @@ def iqa_tiles(x: torch.Tensor, y: torch.Tensor, NT: int, *, C1: float = C_DEFAUL
         st = lib.iqa_tiles_cfg(_ptr(x), _ptr(y), N, NT, D, C1, C2, C, _ptr(lo), _ptr(ao),
                                _ptr(so), cfg_p, _stream_handle(dev, stream))
     _lib.check(st, "iqa_tiles")
+    _mark_used(stream, *(t for k, t in (("lisi", lo), ("auglisi", ao), ("sums", so))
+                         if k not in out))
     return TileResult(lo, ao, so)
 
 
@@ -112,6 +124,8 @@ def lisi_tiles(x: torch.Tensor, y: torch.Tensor, NT: int, *, C1: float = C_DEFAU
         st = _lib.load().lisi_tiles(_ptr(x), _ptr(y), N, NT, D, C1, C2, _ptr(lo),
                                     _stream_handle(x.device, stream))
     _lib.check(st, "lisi_tiles")
+    if out is None:
+        _mark_used(stream, lo)
     return lo
 
 
@@ -125,6 +139,8 @@ def auglisi_tiles(x: torch.Tensor, y: torch.Tensor, NT: int, *, C: float = C_DEF
         st = _lib.load().auglisi_tiles(_ptr(x), _ptr(y), N, NT, C, _ptr(ao),
                                        _stream_handle(x.device, stream))
     _lib.check(st, "auglisi_tiles")
+    if out is None:
+        _mark_used(stream, ao)
     return ao
 
 
@@ -187,6 +203,7 @@ def merge_tiles(sums: torch.Tensor, f: int, *, C1: float = C_DEFAULT, C2: float 
         st = _lib.load().iqa_merge_tiles(sums.data_ptr(), ns, f, D, C2, C, lo.data_ptr(),
                                          ao.data_ptr(), so.data_ptr(), _stream_handle(dev, stream))
     _lib.check(st, "iqa_merge_tiles")
+    _mark_used(stream, lo, ao, so)
     return TileResult(lo, ao, so)
 
 
