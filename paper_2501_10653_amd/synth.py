@@ -181,6 +181,28 @@ def random_pair(N: int, rng: np.random.Generator, neg_frac: float = 0.3,
     return x.astype(np.float32), y.astype(np.float32)
 
 
+_STREAM_TRANSIENT = 20
+
+
+def bright_transient_pair(N: int = 2048, NT: int = 64, amp: float = 8.0,
+                          seed: int = 21) -> Tuple[np.ndarray, np.ndarray, Dict]:
+    """The paper-shape field in both images (independent noise, no source
+    removed) plus one bright source of amplitude `amp` (FWHM 4 px, well above
+    the field's brightest at 2) in the first image only.  In the tiles around
+    it P/(Sx+Sy+C) exceeds 1/2, the regime in which augLISI = 1 - P/(Sx+Sy+C)
+    loses relative accuracy."""
+    base = PairSpec(N=N, NT=NT, n_src=scaled_count(33, N, 1), amp_lo=1e-3, amp_hi=2.0,
+                    fwhm=4.0, noise_sigma=1e-4, n_drop=0, seed=seed)
+    x, y, meta = make_pair(base)
+    rng = np.random.default_rng((seed, _STREAM_TRANSIENT))
+    sig = base.fwhm * FWHM_TO_SIGMA
+    r0, c0 = rng.uniform(3 * sig, N - 1 - 3 * sig, 2)
+    x = np.ascontiguousarray(
+        x.astype(np.float64) + render_sources(N, [r0], [c0], [amp], base.fwhm), dtype=np.float32)
+    meta = dict(meta, transient=(float(r0), float(c0), float(amp)))
+    return x, y, meta
+
+
 _STREAM_SNAPSHOT = 10
 
 

@@ -24,7 +24,9 @@ OUT = os.environ.get("IQA_PRECISION_REPORT")
 
 WORKLOADS = [("small 256/32", synth.spec_small()), ("paper 2048/64", synth.spec_paper_shape())] + \
     [(f"sweep {N}/{NT}", synth.spec_sweep(N, NT)) for N in (1024, 2048, 4096, 8192)
-     for NT in (16, 32, 64, 128, 256)]
+     for NT in (16, 32, 64, 128, 256)] + \
+    [("bright transient amp 2, 2048/64", (lambda: synth.bright_transient_pair(2048, 64, amp=2.0), 64)),
+     ("bright transient amp 8, 2048/16", (lambda: synth.bright_transient_pair(2048, 16, amp=8.0), 16))]
 
 
 def stats(g, o):
@@ -35,10 +37,15 @@ def stats(g, o):
 def test_precision_report():
     report = []
     for name, spec in WORKLOADS:
-        x, y, _ = synth.make_pair(spec)
-        res = iqa_tiles(to_dev(x), to_dev(y), spec.NT, sums=True)
+        if isinstance(spec, tuple):
+            x, y, _ = spec[0]()
+            NT = spec[1]
+        else:
+            x, y, _ = synth.make_pair(spec)
+            NT = spec.NT
+        res = iqa_tiles(to_dev(x), to_dev(y), NT, sums=True)
         torch.cuda.synchronize()
-        ol, oa, osum = oracle_for(x, y, spec.NT)
+        ol, oa, osum = oracle_for(x, y, NT)
         gl = res.lisi.cpu().numpy().ravel()
         ga = res.auglisi.cpu().numpy().ravel()
         gs = res.sums.cpu().numpy()

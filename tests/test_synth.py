@@ -56,3 +56,16 @@ def test_serving_recipe():
     t = synth.poisson_arrivals(10000, 5000, seed=2)
     assert np.all(np.diff(t) >= 0)
     assert abs(5000 / (t[-1] / 1e9) - 10000) < 600
+
+
+def test_bright_transient_pair_is_seeded_and_only_in_the_first_image():
+    x1, y1, m1 = synth.bright_transient_pair(256, 32, amp=8.0, seed=4)
+    x2, y2, m2 = synth.bright_transient_pair(256, 32, amp=8.0, seed=4)
+    assert x1.dtype == np.float32 and x1.shape == (256, 256) and x1.flags.c_contiguous
+    assert np.array_equal(x1, x2) and np.array_equal(y1, y2)
+    r0, c0, amp = m1["transient"]
+    i, j = int(round(r0)), int(round(c0))
+    # the transient's peak stands in the first image only
+    assert x1[i, j] - y1[i, j] > 0.5 * amp
+    far = (abs(np.arange(256)[:, None] - r0) > 20) | (abs(np.arange(256)[None, :] - c0) > 20)
+    assert np.abs(x1 - y1)[far].max() < 0.05
