@@ -50,9 +50,10 @@
  *   of magnitude at most 2^50, so that the per-tile sums stay finite in FP32.
  * Precision.  Per-pixel terms are FP32; tile sums are Kahan-compensated FP32;
  *   augLISI is finalised in double-float arithmetic; the final quotients are
- *   within one unit in the last place.  Worst-case relative error of every
- *   output against exact arithmetic: about 3.3e-6 (55 units of FP32
- *   roundoff; measured: below 6e-7).  Results are bitwise
+ *   within one unit in the last place.  Worst-case error against exact
+ *   arithmetic: about 3.3e-6 (55 units of FP32 roundoff) relative to the
+ *   value for the sums and LISI, and relative to max(|augLISI|,
+ *   P/(Sx+Sy+C)) for augLISI; measured: below 6e-7.  Results are bitwise
  *   reproducible run to run for a given launch configuration (no floating-point
  *   atomics) and bitwise symmetric under swapping x and y.
  */
