@@ -438,7 +438,9 @@ def main(argv=None) -> int:
     if not args.no_extras:
         extras = run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling,
                             lisi_tiles, auglisi_tiles, iqa_tiles, cfg, bytes_pair)
+        extras["kernel_frac_of_read_ceiling"] = round(gbs / extras["read_ceiling_gbs"], 4)
         batched = run_same_shape_batch(torch, xs, ys, NT, stream, bytes_pair, gbs)
+        batched["frac_of_read_ceiling"] = round(batched["gbs"] / extras["read_ceiling_gbs"], 4)
 
     traffic = traffic_record(N, NT, cfg)
     roofline = {
