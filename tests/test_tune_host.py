@@ -1,0 +1,67 @@
+"""Host-side logic of the autotuner and of the build step that compiles its
+results in: candidate shapes are valid, and the generated table holds
+exactly what the JSON cache says."""
+
+from __future__ import annotations
+
+import json
+
+import pytest
+
+from paper_2501_10653_amd import build, tune
+from paper_2501_10653_amd.iqa import check_cfg
+
+
+@pytest.mark.parametrize("N,NT", tune.SWEEP + tune.EXTRA)
+def test_single_candidates_are_valid_and_varied(N, NT):
+    cands = tune.candidates_single(N, NT)
+    assert cands, (N, NT)
+    for c in cands:
+        assert check_cfg(N, NT, c) == 0, c
+        assert c["vec"] == 4
+    # the search covers more than one wave count and row-phase count
+    assert len({c["waves"] for c in cands}) > 1
+    assert len({(c["rp"], c["ksplit"]) for c in cands}) > 1
+
+
+@pytest.mark.parametrize("NT", [32, 64, 128])
+def test_batch_candidates_follow_the_batch_rules(NT):
+    cands = tune.candidates_batch(NT)
+    assert cands
+    for c in cands:
+        # batch geometry: vec 4, one wave per tile group, no row split, unroll 8
+        assert (c["vec"], c["waves"], c["ksplit"], c["unroll"]) == (4, 1, 1, 8)
+        assert check_cfg(4096, NT, c) == 0, c
+
+
+def test_tuned_table_matches_the_json_cache(tmp_path):
+    doc = {
+        "single": {"2048x64": {"cfg": dict(vec=4, waves=4, unroll=8, seg=16, rp=2, ksplit=1)},
+                   "1024x256": {"cfg": dict(vec=4, waves=4, unroll=8, seg=64, rp=1, ksplit=8)}},
+        "batch": {"64": dict(vec=4, waves=1, unroll=8, seg=16, rp=2, ksplit=1)},
+        "batch_waves": 4096,
+    }
+    src = tmp_path / "cache.json"
+    src.write_text(json.dumps(doc))
+    inc = tmp_path / "table.inc"
+    assert build.write_tuned_table(str(src), str(inc)) == 3
+    text = inc.read_text()
+    assert "{1024, 256, 0, {4, 4, 8, 64, 1, 8}}," in text
+    assert "{2048, 64, 0, {4, 4, 8, 16, 2, 1}}," in text
+    assert "{0, 64, 1, {4, 1, 8, 16, 2, 1}}," in text
+    assert "kTunedCount = 3;" in text and "kTunedBatchWaves = 4096;" in text
+    # no cache: an empty table that still compiles
+    empty = tmp_path / "empty.inc"
+    assert build.write_tuned_table(str(tmp_path / "missing.json"), str(empty)) == 0
+    assert "kTunedCount = 0;" in empty.read_text()
+
+
+def test_committed_cache_entries_are_valid():
+    with open(build.TUNED_JSON) as fh:
+        doc = json.load(fh)
+    for key, rec in doc["single"].items():
+        N, NT = (int(v) for v in key.split("x"))
+        assert check_cfg(N, NT, rec["cfg"]) == 0, key
+    for NT, cfg in doc["batch"].items():
+        assert check_cfg(4096, int(NT), cfg) == 0, NT
+    assert doc["batch_waves"] >= 4 and doc["batch_waves"] % 4 == 0
