@@ -44,6 +44,21 @@ class ServedRequest:
 
 
 class Server:
+    """A continuous-batching server on the current HIP device.
+
+    budget_bytes      admission cap: bytes held by admitted, unfinished requests
+                      (a request holds its snapshot plus its outputs).
+    streams           launch slots, i.e. batches in flight (1..16).
+    max_batch         requests per launch.
+    waves             persistent waves per launch (0: the tuned default).
+    host_arena_bytes  per slot: device room for snapshots given in pinned host
+                      memory (0: device snapshots only).
+    C1, C2, C, D      the Eq. 1 / Eq. 2 constants of every request.
+    idle_spin_us      how long the scheduler keeps polling after its last work
+                      before it sleeps (polling occupies one CPU core; a wake-up
+                      from sleep costs several microseconds of latency).
+    """
+
     def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
                  waves: int = 0, host_arena_bytes: int = 0, C1: float = C_DEFAULT,
                  C2: float = C_DEFAULT, C: float = C_DEFAULT, D: Optional[float] = None,
