@@ -177,7 +177,7 @@ def candidates_batch(NT: int) -> List[dict]:
 
 
 def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 1024, 2048, 4096),
-               copies: int = 8, waves_list: Sequence[int] = (1024, 2048, 4096),
+               copies: int = 8, waves_list: Sequence[int] = (1024, 2048, 4096, 8192, 16384),
                log=None) -> Tuple[Dict[int, dict], int, list]:
     """Per-N_T batch geometry and the persistent wave count, timed on a batch
     of `copies` pairs of every (N, N_T)."""
@@ -215,22 +215,30 @@ def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 102
         for N in Ns:
             lib.iqa_tune_set(N, NT, _lib.TUNE_BATCH, LaunchCfg.from_dict(best[NT]))
         del pairs
-    # persistent waves on the mixed batch
+    # Persistent waves, scored on two batches: a large mixed one (every N and
+    # N_T) and a small one (three pairs, as a server sees at moderate load),
+    # where too few waves leave a second round of units for some of them.
     mixed = [(proto[N][0].clone(), proto[N][1].clone(), NT) for N in Ns for NT in NTs
              for _ in range(max(1, copies // 2))]
+    smalls = [[(proto[N][0].clone(), proto[N][1].clone(), NT)
+               for N, NT in zip(Ns[-3:], (32, 64, 64))] for _ in range(8)]
     evict_infinity_cache(torch, dev)
     total = sum(8 * p[0].shape[0] ** 2 for p in mixed)
-    wres = []
+    t_mixed, t_small = {}, {}
     for w in waves_list:
         b = Batch(mixed, waves=w)
-        us = timer.per_launch_us(lambda i: b.run(stream=s), 4)
-        wres.append((us, w))
-        log_rows.append({"NT": "mixed", "waves": w, "us": us, "gbs": total / us / 1e3})
+        t_mixed[w] = timer.per_launch_us(lambda i: b.run(stream=s), 4)
+        bs = [Batch(p, waves=w) for p in smalls]
+        t_small[w] = timer.per_launch_us(lambda i: bs[i % len(bs)].run(stream=s), 32)
+        log_rows.append({"NT": "mixed", "waves": w, "us": t_mixed[w],
+                         "gbs": total / t_mixed[w] / 1e3, "small_batch_us": t_small[w]})
         if log:
-            log(f"  batch mixed waves={w} {us:9.1f} us {total / us / 1e3:7.0f} GB/s")
-    wres.sort()
+            log(f"  batch waves={w} mixed {t_mixed[w]:9.1f} us {total / t_mixed[w] / 1e3:7.0f} GB/s"
+                f"  small {t_small[w]:7.2f} us")
+    m0, s0 = min(t_mixed.values()), min(t_small.values())
+    best_w = min(waves_list, key=lambda w: t_mixed[w] / m0 + t_small[w] / s0)
     lib.iqa_tune_clear()
-    return best, wres[0][1], log_rows
+    return best, best_w, log_rows
 
 
 def load(path: str = DEFAULT_OUT) -> Optional[dict]:
