@@ -238,15 +238,11 @@ def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 3
     return summ
 
 
-def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
-    """Ragged batch: `count` pairs with N uniform over {512, 1024, 2048, 4096}
-    and N_T over {32, 64, 128}, 20% with 1-5 faintest sources removed and the
-    rest noise-only.  One prototype pair is generated per (N, kind) and copied
-    into distinct device buffers for every pair (timing is content-independent).
-    Times one persistent launch (eager and graph-replayed) against `count`
-    single-pair launches (eager and graph-replayed)."""
-    from paper_2501_10653_amd import iqa_tiles, synth
-    from paper_2501_10653_amd.batch import Batch
+def ragged_pairs(torch, dev, count: int = 256, seed: int = 7):
+    """The ragged-batch workload's pairs: one prototype pair per (N, transient
+    or not), copied into distinct device buffers for every pair (timing is
+    content-independent)."""
+    from paper_2501_10653_amd import synth
     specs = synth.ragged_specs(count=count, seed=seed)
     proto = {}
     for N in sorted({sp.N for sp in specs}):
@@ -263,6 +259,19 @@ def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
     del proto
     from paper_2501_10653_amd.tune import evict_infinity_cache
     evict_infinity_cache(torch, dev)
+    return pairs
+
+
+def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
+    """Ragged batch: `count` pairs with N uniform over {512, 1024, 2048, 4096}
+    and N_T over {32, 64, 128}, 20% with 1-5 faintest sources removed and the
+    rest noise-only.  One prototype pair is generated per (N, kind) and copied
+    into distinct device buffers for every pair (timing is content-independent).
+    Times one persistent launch (eager and graph-replayed) against `count`
+    single-pair launches (eager and graph-replayed)."""
+    from paper_2501_10653_amd import iqa_tiles
+    from paper_2501_10653_amd.batch import Batch
+    pairs = ragged_pairs(torch, dev, count, seed)
     total = sum(8 * p[0].shape[0] ** 2 for p in pairs)
     s = torch.cuda.Stream(dev)
 
@@ -332,6 +341,24 @@ def main(argv=None) -> int:
         return 1
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.workload == "ragged" and args.profile:
+        # Counter runs: three eager launches of the batch, then a copy of known
+        # size (256 MiB read + 256 MiB written) that calibrates the counters.
+        from paper_2501_10653_amd.batch import Batch
+        pairs = ragged_pairs(torch, dev)
+        b = Batch(pairs)
+        for _ in range(3):
+            b.run()
+        src = torch.empty(64 * 2 ** 20, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": True, "workload": "ragged", "pairs": len(pairs),
+                          "bytes": sum(8 * p[0].shape[0] ** 2 for p in pairs),
+                          "units": b.units, "waves": b.waves}), flush=True)
+        return 0
 
     if args.workload == "ragged":
         r = run_ragged(torch, dev)
