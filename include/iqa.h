@@ -247,7 +247,11 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
  *                start): wave g processes units g, g+waves, g+2*waves, ...
  * Allocates nothing and calls nothing but the launch, so it can be captured
  * into a HIP graph.  The descriptor contents are not validated on the device:
- * pass exactly what iqa_batch_describe wrote. */
+ * pass exactly what iqa_batch_describe wrote, and a device buffer that holds
+ * at least `count` descriptors.  A unit number that falls outside its pair's
+ * tile groups (total_units larger than described, or count smaller) is
+ * skipped by the kernel, never read from; tiles of units beyond total_units
+ * are left unwritten. */
 iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
                              int64_t waves, void *stream);
 
@@ -257,6 +261,9 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
 /* The same launch for a small batch whose descriptors stay in host memory:
  *   descs_host   host copy of the descriptors from iqa_batch_describe, for
  *                1 <= count <= IQA_BATCH_INLINE_MAX pairs (else IQA_ERR_SHAPE).
+ *   total_units  must be the number iqa_batch_describe returned for exactly
+ *                these descriptors: the host checks that pair i's units
+ *                follow pair i-1's and that they add up (else IQA_ERR_CONFIG).
  * The descriptors travel by value in the kernel arguments, so no device table
  * and no copy precede the launch (one enqueue instead of two), and the host
  * buffer may be reused as soon as the call returns.  Results are bitwise

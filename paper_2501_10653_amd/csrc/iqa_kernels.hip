@@ -556,7 +556,11 @@ __device__ __forceinline__ void batch_body(const BatchDesc *descs, int count, in
         }
         const int pi = __builtin_amdgcn_readfirstlane(lo);
         const KArgs a = descs[pi].a;
-        const int grp = (int)(u - descs[pi].unit_begin);
+        // A unit outside the pair's tile groups (a unit count or pair count
+        // that does not match the table) is skipped, never read.
+        const int64_t g64 = u - descs[pi].unit_begin;
+        if (g64 < 0 || g64 >= (int64_t)a.ns * a.ngx) continue;
+        const int grp = (int)g64;
         const int ty = udiv(grp, a.ngx_m, a.ngx);
         const int txg = grp - ty * a.ngx;
         const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, 0, lane)
@@ -706,12 +710,33 @@ __global__ __launch_bounds__(256) void read_ceiling_kernel(const float4 *__restr
 
 thread_local int g_last_hip_error = 0;
 
-using LaunchFn = void (*)(const KArgs &, unsigned, hipStream_t);
+// Every launch goes through hipLaunchKernel and reports its own status (not a
+// sticky error some earlier, unrelated call left behind).  The arguments take
+// the kernel's own parameter types, so a mismatch does not compile.
+template <typename T>
+struct same_type {
+    using type = T;
+};
+
+template <typename... P>
+hipError_t launch_kernel(void (*fn)(P...), unsigned grid, unsigned block, hipStream_t s,
+                         typename same_type<P>::type... args) {
+    void *argv[] = {static_cast<void *>(&args)...};
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(block), argv, 0,
+                           s);
+}
+
+iqa_status hip_status(hipError_t e) {
+    if (e == hipSuccess) return IQA_OK;
+    g_last_hip_error = (int)e;
+    return IQA_ERR_HIP;
+}
+
+using LaunchFn = hipError_t (*)(const KArgs &, unsigned, hipStream_t);
 
 template <int VEC, int WAVES, int U, int MODE, bool WIDE>
-void launch_impl(const KArgs &a, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((tiles_kernel<VEC, WAVES, U, MODE, WIDE>), dim3(grid),
-                       dim3(WAVES * kWave), 0, s, a);
+hipError_t launch_impl(const KArgs &a, unsigned grid, hipStream_t s) {
+    return launch_kernel(&tiles_kernel<VEC, WAVES, U, MODE, WIDE>, grid, WAVES * kWave, s, a);
 }
 
 template <int VEC, int WAVES, int U, bool WIDE>
@@ -757,20 +782,13 @@ LaunchFn pick(const iqa_launch_cfg &c, int mode, bool wide) {
     return nullptr;
 }
 
-void launch_combine(const KArgs &a, int mode, hipStream_t s) {
+hipError_t launch_combine(const KArgs &a, int mode, hipStream_t s) {
     const int64_t n = (int64_t)a.ns * a.ns;
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    switch (mode) {
-        case kLisi:
-            hipLaunchKernelGGL(combine_kernel<kLisi>, dim3(blocks), dim3(256), 0, s, a);
-            break;
-        case kAug:
-            hipLaunchKernelGGL(combine_kernel<kAug>, dim3(blocks), dim3(256), 0, s, a);
-            break;
-        default:
-            hipLaunchKernelGGL(combine_kernel<kBoth>, dim3(blocks), dim3(256), 0, s, a);
-            break;
-    }
+    void (*fn)(KArgs) = mode == kLisi  ? &combine_kernel<kLisi>
+                        : mode == kAug ? &combine_kernel<kAug>
+                                       : &combine_kernel<kBoth>;
+    return launch_kernel(fn, blocks, 256, s, a);
 }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -1026,17 +1044,9 @@ iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, f
     if (prepare_only) return IQA_OK;
 
     fill_args(a, x, y, N, NT, D, C1, C2, C, lisi, aug, sums, c, g);
-    fn(a, (unsigned)g.grid, s);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && c.ksplit > 1) {
-        launch_combine(a, mode, s);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) {
-        g_last_hip_error = (int)e;
-        return IQA_ERR_HIP;
-    }
-    return IQA_OK;
+    hipError_t e = fn(a, (unsigned)g.grid, s);
+    if (e == hipSuccess && c.ksplit > 1) e = launch_combine(a, mode, s);
+    return hip_status(e);
 }
 
 iqa_status check_common(const float *x, const float *y, int64_t N, int64_t NT) {
@@ -1203,15 +1213,10 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
         return IQA_ERR_CONFIG;
     const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
                                              (total_units + kBatchWaves - 1) / kBatchWaves);
-    hipLaunchKernelGGL(batch_kernel<kBatchUnroll>, dim3((unsigned)blocks),
-                       dim3(kBatchWaves * kWave), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const BatchDesc *>(descs_dev), (int)count, total_units);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        g_last_hip_error = (int)e;
-        return IQA_ERR_HIP;
-    }
-    return IQA_OK;
+    return hip_status(launch_kernel(&batch_kernel<kBatchUnroll>, (unsigned)blocks,
+                                    kBatchWaves * kWave, static_cast<hipStream_t>(stream),
+                                    static_cast<const BatchDesc *>(descs_dev), (int)count,
+                                    total_units));
 }
 
 iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count, int64_t total_units,
@@ -1223,18 +1228,21 @@ iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count, int64
     InlineDescs in;
     std::memset(&in, 0, sizeof(in));
     std::memcpy(in.d, descs_host, (size_t)count * sizeof(BatchDesc));
+    // The table is on the host here, so its unit numbering is checked: pair i
+    // starts where pair i - 1 ends, and the pairs cover exactly total_units.
+    int64_t next = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const KArgs &a = in.d[i].a;
+        if (in.d[i].unit_begin != next || a.ns < 1 || a.ngx < 1) return IQA_ERR_CONFIG;
+        next += (int64_t)a.ns * a.ngx;
+    }
+    if (next != total_units) return IQA_ERR_CONFIG;
     in.units = total_units;
     in.count = (int32_t)count;
     const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
                                              (total_units + kBatchWaves - 1) / kBatchWaves);
-    hipLaunchKernelGGL(batch_kernel_inline<kBatchUnroll>, dim3((unsigned)blocks),
-                       dim3(kBatchWaves * kWave), 0, static_cast<hipStream_t>(stream), in);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        g_last_hip_error = (int)e;
-        return IQA_ERR_HIP;
-    }
-    return IQA_OK;
+    return hip_status(launch_kernel(&batch_kernel_inline<kBatchUnroll>, (unsigned)blocks,
+                                    kBatchWaves * kWave, static_cast<hipStream_t>(stream), in));
 }
 
 iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D, float C2,
@@ -1247,14 +1255,8 @@ iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D,
     const int64_t np = ns / f;
     if (np * np > INT_MAX) return IQA_ERR_SHAPE;
     MergeArgs m{sums_in, ns, f, D, C2, C, lisi, auglisi, sums_out};
-    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)(np * np)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), m);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        g_last_hip_error = (int)e;
-        return IQA_ERR_HIP;
-    }
-    return IQA_OK;
+    return hip_status(launch_kernel(&merge_kernel, (unsigned)(np * np), 256,
+                                    static_cast<hipStream_t>(stream), m));
 }
 
 iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blocks,
@@ -1264,15 +1266,9 @@ iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blo
     if (!aligned(buf, 16) || !aligned(out, 4)) return IQA_ERR_ALIGN;
     const int64_t n4 = n / 4;
     const int64_t per = (n4 + blocks - 1) / blocks;
-    hipLaunchKernelGGL(read_ceiling_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), reinterpret_cast<const float4 *>(buf),
-                       n4, per, out);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        g_last_hip_error = (int)e;
-        return IQA_ERR_HIP;
-    }
-    return IQA_OK;
+    return hip_status(launch_kernel(&read_ceiling_kernel, (unsigned)blocks, 256,
+                                    static_cast<hipStream_t>(stream),
+                                    reinterpret_cast<const float4 *>(buf), n4, per, out));
 }
 
 const char *iqa_status_str(int status) {

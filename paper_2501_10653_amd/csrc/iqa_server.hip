@@ -87,7 +87,8 @@ struct iqa_server {
     int64_t in_flight_bytes = 0, peak_in_flight_bytes = 0;
     int64_t batches = 0, max_batch_seen = 0, rejected = 0;
     bool stop = false;
-    int last_hip_error = 0;
+    // Written by the scheduler thread, read by get_stats from any thread.
+    std::atomic<int> last_hip_error{0};
 
     std::deque<Pending> pending;  // scheduler-owned: admitted order
     std::thread worker;
@@ -449,7 +450,7 @@ iqa_status iqa_server_get_stats(iqa_server *sv, iqa_server_stats *st) {
     st->max_batch = sv->max_batch_seen;
     st->in_flight_bytes = sv->in_flight_bytes;
     st->peak_in_flight_bytes = sv->peak_in_flight_bytes;
-    st->last_hip_error = sv->last_hip_error;
+    st->last_hip_error = sv->last_hip_error.load();
     return IQA_OK;
 }
 

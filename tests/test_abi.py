@@ -177,6 +177,26 @@ def test_inline_batch_launch_validation():
     assert f"#define IQA_BATCH_INLINE_MAX {_lib.BATCH_INLINE_MAX}" in header
 
 
+def test_inline_batch_checks_the_unit_numbering():
+    """The inline launch holds the descriptors on the host, so a unit count
+    or pair order that does not match what iqa_batch_describe wrote is refused
+    before anything is launched."""
+    import numpy as np
+    lib = _lib.load()
+    arr = make_pairs(3)
+    buf = np.zeros(3 * _lib.BATCH_DESC_BYTES, np.uint8)
+    units = ctypes.c_int64(-1)
+    assert lib.iqa_batch_describe(arr, 3, buf.ctypes.data, ctypes.byref(units)) == OK
+    u = units.value
+    for count, total in ((3, u + 1), (3, u - 1), (2, u), (3, 2 * u)):
+        assert lib.iqa_tiles_batched_inline(buf.ctypes.data, count, total, 2048, None) == CONFIG
+    swapped = buf.copy().reshape(3, -1)
+    swapped[[0, 1]] = swapped[[1, 0]]
+    # pairs 0 and 1 have the same geometry, so swapping them keeps the sum but
+    # not the numbering: pair 0 then claims to start at pair 1's first unit
+    assert lib.iqa_tiles_batched_inline(swapped.ctypes.data, 3, u, 2048, None) == CONFIG
+
+
 def test_tune_registry():
     lib = _lib.load()
     lib.iqa_tune_clear()

@@ -123,6 +123,34 @@ def test_inline_descriptors_equal_device_table(ragged):
         Batch(dev[:17] if len(dev) >= 17 else dev * 2, inline=True)
 
 
+def test_units_outside_the_table_are_skipped(ragged):
+    """A table launch told of more units than described, and of fewer pairs
+    than the table holds: the units past the pairs it was given are skipped.
+    The pairs launched come out bitwise as in the full batch; the others keep
+    what their outputs held."""
+    import ctypes
+    from paper_2501_10653_amd import _lib
+    host, dev = ragged
+    sub = [p for p in dev if p[2] % 4 == 0][:6]
+    full = Batch(sub, inline=False)
+    full.run()
+    part = Batch(sub, inline=False)
+    for r in part.results:
+        r.lisi.fill_(-1.0)
+        r.auglisi.fill_(-1.0)
+    torch.cuda.synchronize()
+    k = 4
+    st = _lib.load().iqa_tiles_batched(part.descs.data_ptr(), k, part.units + 1000, part.waves,
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    torch.cuda.synchronize()
+    for i, (r0, r1) in enumerate(zip(full.results, part.results)):
+        if i < k:
+            assert same(r0.lisi, r1.lisi) and same(r0.auglisi, r1.auglisi), i
+        else:
+            assert bool((r1.lisi == -1.0).all()) and bool((r1.auglisi == -1.0).all()), i
+
+
 def test_paper_recipe_pairs_in_a_batch():
     """Pairs built like the ragged-batch workload (sources removed in some,
     noise-only changes in the others) at mixed sizes up to 4096."""
