@@ -17,7 +17,7 @@ import torch
 
 from . import _lib
 from ._lib import IqaPair, LaunchCfg
-from .iqa import C_DEFAULT, TileResult, _check_images, _stream_handle, default_D
+from .iqa import C_DEFAULT, TileResult, _check_images, _mark_used, _stream_handle, default_D
 
 
 def default_waves() -> int:
@@ -114,6 +114,10 @@ class Batch:
                                                    self.waves,
                                                    _stream_handle(self.device, stream))
                 _lib.check(st, "iqa_tiles_batched")
+            if self.count:
+                # the outputs and the descriptor table were allocated on torch's
+                # current stream; the launch may run on another torch stream
+                _mark_used(stream, self.descs, *(t for r in self.results for t in r))
             for i in self.single:
                 x, y, NT = self.inputs[i]
                 r = self.results[i]

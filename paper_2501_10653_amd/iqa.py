@@ -65,8 +65,10 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
 def _mark_used(stream, *tensors) -> None:
     """Outputs allocated here on torch's current stream but written on another
     torch stream: tell the caching allocator, so that their memory is not
-    handed out again before that stream has finished with it."""
-    if isinstance(stream, torch.cuda.Stream):
+    handed out again before that stream has finished with it.  Under graph
+    capture nothing runs yet; the captured launches use the memory whenever
+    the graph is replayed, so the caller keeps those tensors alive."""
+    if isinstance(stream, torch.cuda.Stream) and not torch.cuda.is_current_stream_capturing():
         for t in tensors:
             if t is not None:
                 t.record_stream(stream)

@@ -13,7 +13,7 @@ marshals references, requests and completions.  Typical use::
 from __future__ import annotations
 
 import ctypes
-from typing import List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -57,6 +57,12 @@ class Server:
     idle_spin_us      how long the scheduler keeps polling after its last work
                       before it sleeps (polling occupies one CPU core; a wake-up
                       from sleep costs several microseconds of latency).
+
+    The server holds every submitted request (its snapshot and its output
+    tensors) until its completion has been seen: returned by :meth:`poll`, or
+    covered by a :meth:`drain` that succeeded, or by :meth:`close`.  A caller
+    may drop its own reference right after :meth:`submit` without the device
+    writing into memory that torch has handed to another tensor.
     """
 
     def __init__(self, budget_bytes: int, *, streams: int = 4, max_batch: int = 512,
@@ -75,6 +81,21 @@ class Server:
         self.h = h
         self.refs: List[torch.Tensor] = []
         self._next_tag = 0
+        # submitted requests whose completion has not been seen, by tag (FIFO
+        # per tag: tags chosen by the caller need not be unique)
+        self._held: Dict[int, List[ServedRequest]] = {}
+
+    def _hold(self, reqs: Sequence[ServedRequest]) -> None:
+        for r in reqs:
+            self._held.setdefault(r.tag, []).append(r)
+
+    def _release(self, comps: List[dict]) -> None:
+        for c in comps:
+            held = self._held.get(c["tag"])
+            if held:
+                held.pop(0)
+                if not held:
+                    del self._held[c["tag"]]
 
     def add_reference(self, ref: torch.Tensor) -> int:
         if ref.dtype != torch.float32 or ref.dim() != 2 or ref.shape[0] != ref.shape[1] or \
@@ -102,14 +123,22 @@ class Server:
     def submit(self, reqs: Sequence[ServedRequest]) -> None:
         arr = (Request * len(reqs))(*[r.c for r in reqs])
         _lib.check(self._lib.iqa_server_submit(self.h, arr, len(reqs)), "iqa_server_submit")
+        self._hold(reqs)
 
     def poll(self, max_n: int = 4096) -> List[dict]:
+        """Completions not yet returned (at most max_n), in completion order;
+        the requests they name are no longer held by the server."""
         buf = (Completion * max_n)()
         n = self._lib.iqa_server_poll(self.h, buf, max_n)
-        return [_completion(buf[i]) for i in range(n)]
+        comps = [_completion(buf[i]) for i in range(n)]
+        self._release(comps)
+        return comps
 
     def drain(self, timeout_s: float = 60.0) -> None:
+        """Wait until every submitted request has completed (their completions
+        stay available to :meth:`poll`)."""
         _lib.check(self._lib.iqa_server_drain(self.h, int(timeout_s * 1000)), "iqa_server_drain")
+        self._held.clear()
 
     def stats(self) -> dict:
         st = ServerStats()
@@ -127,13 +156,18 @@ class Server:
         st = self._lib.iqa_server_replay(self.h, arr,
                                          times.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                          n, out, int(timeout_s * 1000))
+        if st != 0:
+            # timed out: some of these may still be queued or running
+            self._hold(reqs)
         _lib.check(st, "iqa_server_replay")
         return [_completion(out[i]) for i in range(n)]
 
     def close(self) -> None:
+        """Finish all submitted work and free the server."""
         if self.h:
             _lib.check(self._lib.iqa_server_destroy(self.h), "iqa_server_destroy")
             self.h = None
+            self._held.clear()
 
     def __enter__(self):
         return self

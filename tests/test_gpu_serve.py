@@ -144,3 +144,37 @@ def test_poisson_replay(world):
         r = req.ref_id
         k = [i for i in range(2) if snaps[r][i][1].data_ptr() == req.snapshot.data_ptr()][0]
         assert_parity(req, oracle_for(snaps[r][k][0], refs[r][0], req.NT), what="replay")
+
+
+def test_server_holds_dropped_requests_until_completion_is_seen(world):
+    """A request the caller drops right after submit stays alive (snapshot and
+    outputs) until its completion has been seen: by poll, or by drain."""
+    import gc
+    import time
+    import weakref
+    specs, refs, snaps = world
+    with make_server(refs[:1])[0] as srv:
+        # completion seen through poll
+        req = srv.request(snaps[0][0][1], 0, 32)
+        w = weakref.ref(req)
+        srv.submit([req])
+        del req
+        gc.collect()
+        assert w() is not None
+        comps, deadline = [], time.time() + 30
+        while not comps and time.time() < deadline:
+            comps += srv.poll()
+        assert len(comps) == 1 and comps[0]["status"] == 0
+        gc.collect()
+        assert w() is None
+        # completion covered by drain
+        req = srv.request(snaps[0][1][1], 0, 64)
+        w = weakref.ref(req)
+        srv.submit([req])
+        del req
+        gc.collect()
+        assert w() is not None
+        srv.drain()
+        gc.collect()
+        assert w() is None
+        assert len(srv.poll()) == 1
