@@ -283,9 +283,11 @@ iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count,
  * holds its snapshot, 4*N*N bytes, plus its output matrices), and packs all
  * admitted requests into one batched launch (iqa_tiles_batched_inline up to
  * IQA_BATCH_INLINE_MAX requests, else iqa_tiles_batched) whenever one of
- * `streams` launch slots is free; a slot frees when its batch's completion
- * event fires.  Requests arriving while batches run join the next launch, so
- * batches overlap on the device.  A request's results are bitwise the same
+ * `streams` launch slots is free.  After each batch the slot's stream runs a
+ * one-thread kernel that stores the batch's number into a word of pinned host
+ * memory; the slot frees when the scheduler sees that word change (no HIP
+ * event is recorded or queried per batch).  Requests arriving while batches
+ * run join the next launch, so batches overlap on the device.  A request's results are bitwise the same
  * whatever it is batched with (they equal iqa_tiles_cfg with the batch
  * geometry of iqa_batch_cfg).  All entry points are thread-safe. */
 typedef struct iqa_server iqa_server;

@@ -7,9 +7,16 @@
 // bytes held by admitted, unfinished requests stay under an HBM budget, packs
 // everything admitted into one launch of the persistent batched kernel
 // whenever one of its `streams` launch slots is free, and retires a batch when
-// its completion event has fired.  Requests that arrive while batches run are
+// its completion word says so.  Requests that arrive while batches run are
 // admitted as budget and slots free up and go out with the next launch, so
 // batches overlap on the device (one stream per slot).
+//
+// Completion: after each batch the slot's stream runs a one-thread kernel that
+// stores the batch's sequence number into a word of pinned host memory, and
+// the scheduler polls that word.  Stream order makes the store follow the
+// batch (and any snapshot copies before it).  A HIP event would do the same
+// job, but recording one has a long host-side latency tail (tens of
+// microseconds at the 99th percentile) and its completion is seen later.
 //
 // A request's results do not depend on what it is batched with: each pair in
 // a batch is reduced by its own waves, in a fixed order.
@@ -28,6 +35,16 @@
 #include <vector>
 
 #include "iqa.h"
+
+namespace iqa_srv {
+
+// Publishes a finished batch: stores its sequence number into the slot's
+// completion word (system scope, so the host sees it without any HIP call).
+__global__ void publish_kernel(uint32_t *word, uint32_t seq) {
+    if (threadIdx.x == 0) __hip_atomic_store(word, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+}  // namespace iqa_srv
 
 namespace {
 
@@ -49,11 +66,14 @@ struct Pending {
     int64_t cost = 0;
 };
 
-// One launch slot: its stream, event, pinned descriptor staging, device
-// descriptor table and (for host snapshots) a device snapshot arena.
+// One launch slot: its stream, completion word, pinned descriptor staging,
+// device descriptor table and (for host snapshots) a device snapshot arena.
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    uint32_t *word_host = nullptr;   // pinned, host-coherent completion word
+    uint32_t *word_dev = nullptr;    // the same word as the device sees it
+    uint32_t seq = 0;                // number of the batch in flight
+    int64_t t_checked = 0;           // last time the stream was asked for errors
     void *desc_host = nullptr;
     void *desc_dev = nullptr;
     float *arena = nullptr;      // device, for snapshots copied from the host
@@ -64,6 +84,18 @@ struct Slot {
     int64_t dry_due = 0;         // dry run: when the simulated batch completes
     std::vector<Pending> reqs;
 };
+
+hipError_t launch_publish(const Slot &s) {
+    uint32_t *word = s.word_dev;
+    uint32_t seq = s.seq;
+    void *args[] = {&word, &seq};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&iqa_srv::publish_kernel), dim3(1),
+                           dim3(64), args, 0, s.stream);
+}
+
+// How long a batch may run before the scheduler also asks its stream whether
+// it failed (a failed batch never publishes).
+constexpr int64_t kErrorCheckNs = 1000000;
 
 }  // namespace
 
@@ -86,7 +118,12 @@ struct iqa_server {
     int64_t submitted = 0, completed = 0;
     int64_t in_flight_bytes = 0, peak_in_flight_bytes = 0;
     int64_t batches = 0, max_batch_seen = 0, rejected = 0;
-    bool stop = false;
+    // Set under mu; also read without it by the scheduler loop.
+    std::atomic<bool> stop{false};
+    // intake.size(), published under mu, so that the scheduler loop can see
+    // new work without taking the lock (a spinning loop that takes mu on every
+    // pass delays the submitting threads).
+    std::atomic<int64_t> intake_n{0};
     // Written by the scheduler thread, read by get_stats from any thread.
     std::atomic<int> last_hip_error{0};
 
@@ -169,7 +206,8 @@ bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
         }
     }
     if (ok) {
-        hipError_t e = hipEventRecord(s.done, s.stream);
+        s.seq += 1;
+        hipError_t e = launch_publish(s);
         if (e != hipSuccess) {
             last_hip_error = (int)e;
             ok = false;
@@ -178,6 +216,7 @@ bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
     s.reqs.swap(batch);
     s.busy = true;
     s.t_launch = now_ns();
+    s.t_checked = s.t_launch;
     return ok;
 }
 
@@ -209,17 +248,24 @@ void iqa_server::run() {
     int64_t last_active = now_ns();
     while (true) {
         bool idle = true;
-        {
-            std::unique_lock<std::mutex> lock(mu);
-            if (stop && intake.empty() && pending.empty()) {
-                bool any_busy = false;
-                for (const Slot &s : slots) any_busy |= s.busy;
-                if (!any_busy) break;
-            }
-            if (!intake.empty()) idle = false;
+        if (intake_n.load(std::memory_order_acquire) > 0) {
+            std::lock_guard<std::mutex> lock(mu);
             while (!intake.empty()) {
                 pending.push_back(intake.front());
                 intake.pop_front();
+            }
+            intake_n.store(0, std::memory_order_relaxed);
+            idle = false;
+        }
+        if (stop.load(std::memory_order_acquire) && pending.empty()) {
+            bool any_busy = false;
+            for (const Slot &s : slots) any_busy |= s.busy;
+            if (!any_busy) {
+                // submit refuses new work once stop is set (under mu), so an
+                // empty intake seen under mu stays empty.
+                std::lock_guard<std::mutex> lock(mu);
+                if (intake.empty()) break;
+                continue;
             }
         }
         // Retire finished batches.
@@ -232,15 +278,25 @@ void iqa_server::run() {
                 }
                 continue;
             }
-            const hipError_t q = hipEventQuery(s.done);
-            if (q == hipSuccess) {
+            if (__atomic_load_n(s.word_host, __ATOMIC_ACQUIRE) == s.seq) {
                 retire(s, IQA_OK);
                 idle = false;
-            } else if (q != hipErrorNotReady) {
-                last_hip_error = (int)q;
-                retire(s, IQA_ERR_HIP);
-                idle = false;
+                continue;
             }
+            const int64_t t = now_ns();
+            if (t - s.t_checked < kErrorCheckNs) continue;
+            s.t_checked = t;
+            const hipError_t q = hipStreamQuery(s.stream);
+            if (q == hipErrorNotReady) continue;
+            // The stream has finished (or failed): its publish store, if it
+            // ran, is visible now.
+            if (q == hipSuccess && __atomic_load_n(s.word_host, __ATOMIC_ACQUIRE) == s.seq) {
+                retire(s, IQA_OK);
+            } else {
+                last_hip_error = q == hipSuccess ? (int)hipErrorUnknown : (int)q;
+                retire(s, IQA_ERR_HIP);
+            }
+            idle = false;
         }
         // Launch into a free slot everything the budget admits, in order.
         for (Slot &s : slots) {
@@ -283,17 +339,18 @@ void iqa_server::run() {
         if (!idle) {
             last_active = now_ns();
         } else {
-            std::unique_lock<std::mutex> lock(mu);
             bool any_busy = false;
             for (const Slot &s : slots) any_busy |= s.busy;
             if (any_busy || now_ns() - last_active < opts.idle_spin_ns) {
-                // Poll the events (or, for idle_spin_ns after the last work,
-                // the intake) without sleeping: a wake-up from the condition
-                // variable costs tens of microseconds.
-                lock.unlock();
+                // Poll the completion words (or, for idle_spin_ns after the
+                // last work, the intake count) without sleeping and without
+                // the lock: a wake-up from the condition variable costs tens
+                // of microseconds.
                 std::this_thread::yield();
-            } else if (intake.empty() && !stop) {
-                cv.wait_for(lock, std::chrono::milliseconds(1));
+            } else {
+                std::unique_lock<std::mutex> lock(mu);
+                if (intake.empty() && !stop.load(std::memory_order_relaxed))
+                    cv.wait_for(lock, std::chrono::milliseconds(1));
             }
         }
     }
@@ -322,7 +379,13 @@ iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out) {
     sv->slots.resize(opts->streams);
     for (Slot &s : sv->slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&s.word_host), 64,
+                              hipHostMallocCoherent | hipHostMallocMapped);
+        if (e == hipSuccess) {
+            *s.word_host = 0;
+            e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s.word_dev), s.word_host, 0);
+        }
         if (e == hipSuccess)
             e = hipHostMalloc(&s.desc_host, (size_t)opts->max_batch * IQA_BATCH_DESC_BYTES,
                               hipHostMallocDefault);
@@ -413,6 +476,7 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
         p.cost = request_cost(*sv, r);
         sv->intake.push_back(p);
     }
+    sv->intake_n.store((int64_t)sv->intake.size(), std::memory_order_release);
     sv->submitted += count;
     sv->completed += rejected;
     sv->rejected += rejected;
@@ -513,8 +577,8 @@ iqa_status iqa_server_destroy(iqa_server *sv) {
     if (sv->worker.joinable()) sv->worker.join();
     for (Slot &s : sv->slots) {
         if (s.stream) (void)hipStreamSynchronize(s.stream);
-        if (s.done) (void)hipEventDestroy(s.done);
         if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.word_host) (void)hipHostFree(s.word_host);
         if (s.desc_host) (void)hipHostFree(s.desc_host);
         if (s.desc_dev) (void)hipFree(s.desc_dev);
         if (s.arena) (void)hipFree(s.arena);
