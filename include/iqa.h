@@ -266,7 +266,9 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
  *                follow pair i-1's and that they add up (else IQA_ERR_CONFIG).
  * The descriptors travel by value in the kernel arguments, so no device table
  * and no copy precede the launch (one enqueue instead of two), and the host
- * buffer may be reused as soon as the call returns.  Results are bitwise
+ * buffer may be reused as soon as the call returns.  The argument block holds
+ * 1, 4 or IQA_BATCH_INLINE_MAX descriptors, the smallest that fits `count`:
+ * a launch's host-side cost grows with its argument size.  Results are bitwise
  * those of iqa_tiles_batched on the same descriptors.  Captured into a HIP
  * graph, the launch keeps the descriptors it was given. */
 iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count,

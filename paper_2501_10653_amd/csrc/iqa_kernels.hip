@@ -578,17 +578,20 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel(const BatchD
     batch_body<U>(descs, count, units);
 }
 
-// Up to IQA_BATCH_INLINE_MAX descriptors passed by value in the kernel
-// arguments: no table to copy to the device before the launch.  The waves
-// read the descriptors straight from the kernel-argument segment.
+// Up to CAP descriptors passed by value in the kernel arguments: no table to
+// copy to the device before the launch.  The waves read the descriptors
+// straight from the kernel-argument segment.  Instantiated for CAP = 1, 4 and
+// IQA_BATCH_INLINE_MAX: a launch uses the smallest that holds its batch,
+// because the host-side cost of a launch grows with its argument size.
+template <int CAP>
 struct InlineDescs {
-    BatchDesc d[IQA_BATCH_INLINE_MAX];
+    BatchDesc d[CAP];
     int64_t units;
     int32_t count;
 };
 
-template <int U>
-__global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel_inline(InlineDescs in) {
+template <int U, int CAP>
+__global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel_inline(InlineDescs<CAP> in) {
     batch_body<U>(in.d, in.count, in.units);
 }
 
@@ -1067,6 +1070,18 @@ iqa_status check_outputs_params(float *lisi, float *auglisi, float *sums, float 
     return IQA_OK;
 }
 
+template <int CAP>
+iqa_status launch_inline(const void *descs_host, int64_t count, int64_t total_units,
+                         int64_t blocks, hipStream_t s) {
+    InlineDescs<CAP> in;
+    std::memset(&in, 0, sizeof(in));
+    std::memcpy(in.d, descs_host, (size_t)count * sizeof(BatchDesc));
+    in.units = total_units;
+    in.count = (int32_t)count;
+    return hip_status(launch_kernel(&batch_kernel_inline<kBatchUnroll, CAP>, (unsigned)blocks,
+                                    kBatchWaves * kWave, s, in));
+}
+
 }  // namespace iqa
 
 using namespace iqa;
@@ -1225,24 +1240,22 @@ iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count, int64
     if (count < 1 || count > IQA_BATCH_INLINE_MAX || total_units < 1) return IQA_ERR_SHAPE;
     if (waves < kBatchWaves || waves % kBatchWaves != 0 || waves / kBatchWaves > INT_MAX)
         return IQA_ERR_CONFIG;
-    InlineDescs in;
-    std::memset(&in, 0, sizeof(in));
-    std::memcpy(in.d, descs_host, (size_t)count * sizeof(BatchDesc));
     // The table is on the host here, so its unit numbering is checked: pair i
     // starts where pair i - 1 ends, and the pairs cover exactly total_units.
     int64_t next = 0;
     for (int64_t i = 0; i < count; ++i) {
-        const KArgs &a = in.d[i].a;
-        if (in.d[i].unit_begin != next || a.ns < 1 || a.ngx < 1) return IQA_ERR_CONFIG;
-        next += (int64_t)a.ns * a.ngx;
+        BatchDesc d;
+        std::memcpy(&d, static_cast<const BatchDesc *>(descs_host) + i, sizeof(d));
+        if (d.unit_begin != next || d.a.ns < 1 || d.a.ngx < 1) return IQA_ERR_CONFIG;
+        next += (int64_t)d.a.ns * d.a.ngx;
     }
     if (next != total_units) return IQA_ERR_CONFIG;
-    in.units = total_units;
-    in.count = (int32_t)count;
     const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
                                              (total_units + kBatchWaves - 1) / kBatchWaves);
-    return hip_status(launch_kernel(&batch_kernel_inline<kBatchUnroll>, (unsigned)blocks,
-                                    kBatchWaves * kWave, static_cast<hipStream_t>(stream), in));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (count == 1) return launch_inline<1>(descs_host, count, total_units, blocks, s);
+    if (count <= 4) return launch_inline<4>(descs_host, count, total_units, blocks, s);
+    return launch_inline<IQA_BATCH_INLINE_MAX>(descs_host, count, total_units, blocks, s);
 }
 
 iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D, float C2,

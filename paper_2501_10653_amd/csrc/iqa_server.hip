@@ -124,6 +124,9 @@ struct iqa_server {
     // new work without taking the lock (a spinning loop that takes mu on every
     // pass delays the submitting threads).
     std::atomic<int64_t> intake_n{0};
+    // done.size(), published under mu, so that a poll with nothing to return
+    // (a caller polling in a loop) does not take the lock.
+    std::atomic<int64_t> done_n{0};
     // Written by the scheduler thread, read by get_stats from any thread.
     std::atomic<int> last_hip_error{0};
 
@@ -233,6 +236,7 @@ void iqa_server::retire(Slot &s, int status) {
         c.t_done_ns = t;
         done.push_back(c);
     }
+    done_n.store((int64_t)done.size(), std::memory_order_release);
     completed += (int64_t)s.reqs.size();
     in_flight_bytes -= s.bytes;
     s.reqs.clear();
@@ -477,6 +481,7 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
         sv->intake.push_back(p);
     }
     sv->intake_n.store((int64_t)sv->intake.size(), std::memory_order_release);
+    sv->done_n.store((int64_t)sv->done.size(), std::memory_order_release);
     sv->submitted += count;
     sv->completed += rejected;
     sv->rejected += rejected;
@@ -487,12 +492,14 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
 
 int64_t iqa_server_poll(iqa_server *sv, iqa_completion *out, int64_t max) {
     if (!sv || !out || max <= 0) return 0;
+    if (sv->done_n.load(std::memory_order_acquire) == 0) return 0;
     std::lock_guard<std::mutex> lock(sv->mu);
     int64_t n = 0;
     while (n < max && !sv->done.empty()) {
         out[n++] = sv->done.front();
         sv->done.pop_front();
     }
+    sv->done_n.store((int64_t)sv->done.size(), std::memory_order_relaxed);
     return n;
 }
 

@@ -123,6 +123,22 @@ def test_inline_descriptors_equal_device_table(ragged):
         Batch(dev[:17] if len(dev) >= 17 else dev * 2, inline=True)
 
 
+@pytest.mark.parametrize("k", [1, 2, 4, 5, 15])
+def test_inline_argument_sizes_equal_device_table(ragged, k):
+    """Batches of 1..16 pairs launch with an argument block of 1, 4 or 16
+    descriptors; every size gives the device-table launch's bits."""
+    host, dev = ragged
+    sub = [p for p in dev if p[2] % 4 == 0][:k]
+    table = Batch(sub, sums=True, inline=False)
+    inl = Batch(sub, sums=True)
+    assert inl.inline
+    table.run()
+    inl.run()
+    torch.cuda.synchronize()
+    for r0, r1 in zip(table.results, inl.results):
+        assert same(r0.lisi, r1.lisi) and same(r0.auglisi, r1.auglisi) and same(r0.sums, r1.sums)
+
+
 def test_units_outside_the_table_are_skipped(ragged):
     """A table launch told of more units than described, and of fewer pairs
     than the table holds: the units past the pairs it was given are skipped.
