@@ -186,13 +186,15 @@ iqa_status iqa_merge_tiles(const float *sums_in, int64_t ns, int64_t f, float D,
 
 #define IQA_TUNE_SINGLE 0   /* shape used by iqa_tiles & co. for (N, NT) */
 #define IQA_TUNE_BATCH 1    /* per-pair geometry inside iqa_tiles_batched */
+#define IQA_TUNE_SERVE 2    /* per-pair geometry inside the server's batches */
 
 /* The library's default shapes come from autotuner measurements on gfx950
  * compiled into it, falling back to a heuristic for shapes it has not seen.
  * iqa_tune_set registers a configuration for (N, NT) that takes precedence
  * over both (N == 0: for every N with this NT).  Single-pair entries are used
  * when both images are 16-byte aligned; batch entries must have vec 4,
- * waves 1, ksplit 1 and unroll 8.  IQA_ERR_CONFIG if cfg is invalid for the
+ * ksplit 1, unroll 8 and waves 1 (one wave per tile group) or 4 (the four
+ * waves of a workgroup split each tile group's rows).  IQA_ERR_CONFIG if cfg is invalid for the
  * shape.  Thread-safe; takes effect for calls made after it returns. */
 iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *cfg);
 
@@ -227,13 +229,23 @@ typedef struct iqa_pair {
  * batched results are bitwise equal to iqa_tiles_cfg with this config. */
 iqa_status iqa_batch_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg);
 
+/* The per-pair geometry the server uses for (N, NT) (NT % 4 == 0): its own
+ * tuned entries, chosen for the latency of a lone pair (a server's batches
+ * are small), else iqa_batch_cfg's, which is chosen for the throughput of
+ * large batches.  A served request's results are bitwise equal to
+ * iqa_tiles_cfg with this config. */
+iqa_status iqa_serve_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg);
+
 /* Host-side planning of a batch (no GPU calls).
  *   pairs        host array of `count` pairs; each is validated as iqa_tiles
  *                would, and must also have NT % 4 == 0 (IQA_ERR_CONFIG) and
  *                16-byte aligned images (IQA_ERR_ALIGN).
  *   descs        host buffer of count * IQA_BATCH_DESC_BYTES bytes, filled
  *                with opaque descriptors that embed the device pointers.
- *   total_units  receives the number of work units (tile groups) in all.
+ *   total_units  receives the number of work units in all.  A unit is the
+ *                work of one workgroup of 4 waves: four tile groups of a pair
+ *                whose geometry has one wave per group, or one tile group of
+ *                a pair whose geometry has four (iqa_batch_cfg says which).
  * The caller copies `descs` to device memory (16-byte aligned) unchanged and
  * passes that copy to iqa_tiles_batched; it stays valid as long as the pairs'
  * buffers do, so one copy can be launched (or graph-replayed) many times. */
@@ -244,7 +256,8 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
  *   descs_dev    device copy of the descriptors from iqa_batch_describe.
  *   count, total_units  as given to / returned by iqa_batch_describe.
  *   waves        persistent waves (multiple of 4; 2048 = 8 per CU is a good
- *                start): wave g processes units g, g+waves, g+2*waves, ...
+ *                start): the launch has G = min(waves/4, total_units)
+ *                workgroups, and workgroup b processes units b, b+G, b+2G, ...
  * Allocates nothing and calls nothing but the launch, so it can be captured
  * into a HIP graph.  The descriptor contents are not validated on the device:
  * pass exactly what iqa_batch_describe wrote, and a device buffer that holds
@@ -289,9 +302,10 @@ iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count,
  * one-thread kernel that stores the batch's number into a word of pinned host
  * memory; the slot frees when the scheduler sees that word change (no HIP
  * event is recorded or queried per batch).  Requests arriving while batches
- * run join the next launch, so batches overlap on the device.  A request's results are bitwise the same
- * whatever it is batched with (they equal iqa_tiles_cfg with the batch
- * geometry of iqa_batch_cfg).  All entry points are thread-safe. */
+ * run join the next launch, so batches overlap on the device.  A request's
+ * results are bitwise the same whatever it is batched with: they equal
+ * iqa_tiles_cfg with the geometry of iqa_serve_cfg.  All entry points are
+ * thread-safe. */
 typedef struct iqa_server iqa_server;
 
 typedef struct iqa_server_opts {

@@ -86,6 +86,7 @@ BATCH_DESC_BYTES = 128
 BATCH_INLINE_MAX = 16
 TUNE_SINGLE = 0
 TUNE_BATCH = 1
+TUNE_SERVE = 2
 
 
 class IqaError(RuntimeError):
@@ -135,6 +136,7 @@ def load() -> ctypes.CDLL:
         "iqa_tune_clear": ([], None),
         "iqa_batch_default_waves": ([], ctypes.c_int64),
         "iqa_batch_cfg": ([i64, i64, cfgp], ctypes.c_int),
+        "iqa_serve_cfg": ([i64, i64, cfgp], ctypes.c_int),
         "iqa_batch_describe": ([ctypes.POINTER(IqaPair), i64, vp, ctypes.POINTER(i64)],
                                ctypes.c_int),
         "iqa_tiles_batched": ([vp, i64, i64, i64, vp], ctypes.c_int),

@@ -43,6 +43,7 @@
 #include <vector>
 
 #include "iqa.h"
+#include "iqa_internal.h"
 
 namespace iqa {
 
@@ -463,6 +464,23 @@ __device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int 
     return group_allreduce<MODE>(fold(acc), a.log_grp);
 }
 
+// Pairwise tree over the partial sums of WAVES waves (all non-negative), in a
+// fixed order: the same bits wherever a tile's slices are combined.
+template <int WAVES>
+__device__ __forceinline__ float4 wave_tree(float4 (&v)[WAVES]) {
+#pragma unroll
+    for (int h = 1; h < WAVES; h *= 2) {
+#pragma unroll
+        for (int w = 0; w + h < WAVES; w += 2 * h) {
+            v[w].x += v[w + h].x;
+            v[w].y += v[w + h].y;
+            v[w].z += v[w + h].z;
+            v[w].w += v[w + h].w;
+        }
+    }
+    return v[0];
+}
+
 // ---------------------------------------------------------------------------
 // The tile kernel (one image pair)
 // ---------------------------------------------------------------------------
@@ -501,24 +519,14 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
         if (wave != 0 || lane >= a.ht) return;
         const int txl = txg * a.ht + lane;
         if (txl >= a.ns) return;
-        // Pairwise tree over the waves' partials (all non-negative).
         float4 v[WAVES];
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) v[w] = lds[w][lane];
-#pragma unroll
-        for (int h = 1; h < WAVES; h *= 2) {
-#pragma unroll
-            for (int w = 0; w + h < WAVES; w += 2 * h) {
-                v[w].x += v[w + h].x;
-                v[w].y += v[w + h].y;
-                v[w].z += v[w + h].z;
-                v[w].w += v[w + h].w;
-            }
-        }
+        const float4 t = wave_tree<WAVES>(v);
         if (a.ks == 1) {
-            finalize<MODE>(a, (int64_t)ty * a.ns + txl, acc_of(Sum4{v[0].x, v[0].y, v[0].z, v[0].w}));
+            finalize<MODE>(a, (int64_t)ty * a.ns + txl, acc_of(Sum4{t.x, t.y, t.z, t.w}));
         } else {
-            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + lane] = v[0];
+            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + lane] = t;
         }
     }
 }
@@ -527,28 +535,42 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
 // The batched kernel (many image pairs of mixed N and N_T, one launch)
 // ---------------------------------------------------------------------------
 //
-// Each pair is described by its own geometry (one wave per tile group, no row
-// split) and by the index of its first work unit; a unit is one tile group of
-// one pair.  A persistent grid of independent waves takes units round-robin:
-// wave g does units g, g + W, g + 2W, ... where W is the number of waves.  A
-// pair's results are bitwise equal to a single-pair launch with the same
-// geometry and unroll (waves = 1, ksplit = 1).
+// Each pair is described by its own geometry and by the index of its first
+// work unit.  A unit is the work of one workgroup of kBatchWaves waves:
+//   * a pair whose geometry has one wave per tile group (waves 1) packs
+//     kBatchWaves consecutive tile groups into a unit, wave w taking the
+//     unit's w-th group;
+//   * a pair whose geometry has kBatchWaves waves per tile group gives each
+//     tile group a unit of its own: the waves take its row slices and combine
+//     them in LDS exactly as tiles_kernel does.
+// A persistent grid takes units round-robin: workgroup b does units b, b + G,
+// b + 2G, ... where G is the number of workgroups.  Either way a pair's
+// results are bitwise equal to a single-pair launch with the same geometry
+// and unroll (ksplit 1).
 struct BatchDesc {
     KArgs a;
     int64_t unit_begin;
 };
 static_assert(sizeof(BatchDesc) <= IQA_BATCH_DESC_BYTES, "batch descriptor size");
 
-constexpr int kBatchWaves = 4;   // independent waves per workgroup
+constexpr int kBatchWaves = 4;   // waves per workgroup
+
+// A pair whose waves split its tile groups' rows (rows_wave < NT).
+__host__ __device__ __forceinline__ bool batch_coop(const KArgs &a) { return a.rows_wave != a.NT; }
+
+// Work units of one pair.
+__host__ __device__ __forceinline__ int64_t batch_units(const KArgs &a) {
+    const int64_t groups = (int64_t)a.ns * a.ngx;
+    return batch_coop(a) ? groups : (groups + kBatchWaves - 1) / kBatchWaves;
+}
 
 template <int U>
 __device__ __forceinline__ void batch_body(const BatchDesc *descs, int count, int64_t units) {
+    __shared__ float4 lds[kBatchWaves][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int64_t nw = (int64_t)gridDim.x * kBatchWaves;
-    const int64_t g0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kBatchWaves + wave;
-    for (int64_t u = g0; u < units; u += nw) {
-        // Binary search for the pair whose units contain u.
+    for (int64_t u = xcd_remap(blockIdx.x, gridDim.x); u < units; u += gridDim.x) {
+        // Binary search for the pair whose units contain u (same in every wave).
         int lo = 0, hi = count - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -556,18 +578,42 @@ __device__ __forceinline__ void batch_body(const BatchDesc *descs, int count, in
         }
         const int pi = __builtin_amdgcn_readfirstlane(lo);
         const KArgs a = descs[pi].a;
-        // A unit outside the pair's tile groups (a unit count or pair count
-        // that does not match the table) is skipped, never read.
+        // A unit outside the pair's units (a unit count or pair count that
+        // does not match the table) is skipped, never read.
         const int64_t g64 = u - descs[pi].unit_begin;
-        if (g64 < 0 || g64 >= (int64_t)a.ns * a.ngx) continue;
-        const int grp = (int)g64;
-        const int ty = udiv(grp, a.ngx_m, a.ngx);
-        const int txg = grp - ty * a.ngx;
-        const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, 0, lane)
-                                 : slice_sums<4, U, kBoth, false>(a, ty, txg, 0, lane);
-        const int tx = txg * a.ht + (lane >> a.log_grp);
-        if ((lane & ((1 << a.log_grp) - 1)) == 0 && tx < a.ns)
-            finalize<kBoth>(a, (int64_t)ty * a.ns + tx, acc_of(s));
+        if (g64 < 0 || g64 >= batch_units(a)) continue;
+        const bool leader = (lane & ((1 << a.log_grp) - 1)) == 0;
+        if (!batch_coop(a)) {
+            const int64_t grp64 = g64 * kBatchWaves + wave;
+            if (grp64 >= (int64_t)a.ns * a.ngx) continue;
+            const int grp = (int)grp64;
+            const int ty = udiv(grp, a.ngx_m, a.ngx);
+            const int txg = grp - ty * a.ngx;
+            const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, 0, lane)
+                                     : slice_sums<4, U, kBoth, false>(a, ty, txg, 0, lane);
+            const int tx = txg * a.ht + (lane >> a.log_grp);
+            if (leader && tx < a.ns) finalize<kBoth>(a, (int64_t)ty * a.ns + tx, acc_of(s));
+        } else {
+            // Workgroup-uniform branch: every wave reaches both barriers.
+            const int grp = (int)g64;
+            const int ty = udiv(grp, a.ngx_m, a.ngx);
+            const int txg = grp - ty * a.ngx;
+            const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, wave, lane)
+                                     : slice_sums<4, U, kBoth, false>(a, ty, txg, wave, lane);
+            if (leader) lds[wave][lane >> a.log_grp] = float4{s.A, s.P, s.X, s.Y};
+            __syncthreads();
+            if (wave == 0 && lane < a.ht) {
+                const int txl = txg * a.ht + lane;
+                if (txl < a.ns) {
+                    float4 v[kBatchWaves];
+#pragma unroll
+                    for (int w = 0; w < kBatchWaves; ++w) v[w] = lds[w][lane];
+                    const float4 t = wave_tree<kBatchWaves>(v);
+                    finalize<kBoth>(a, (int64_t)ty * a.ns + txl, acc_of(Sum4{t.x, t.y, t.z, t.w}));
+                }
+            }
+            __syncthreads();   // the LDS slots are reused by the next unit
+        }
     }
 }
 
@@ -947,6 +993,14 @@ iqa_launch_cfg batch_cfg(int64_t N, int64_t NT) {
     return c;
 }
 
+// Per-pair geometry in the server's batches: its own tuned entries (chosen
+// for a lone pair's latency), else the ragged-batch geometry.
+iqa_launch_cfg serve_cfg(int64_t N, int64_t NT) {
+    iqa_launch_cfg c;
+    if (tuned_lookup(N, NT, IQA_TUNE_SERVE, &c)) return c;
+    return batch_cfg(N, NT);
+}
+
 // Per (device, stream) workspace for split partials.  Partials are written by
 // tiles_kernel and read by combine_kernel in the same stream order, so one
 // buffer per stream is enough; concurrent streams get their own.  A buffer
@@ -1154,13 +1208,15 @@ iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *c
     // N == 0 registers the entry for every image size with this tile size.
     iqa_status st = check_shape(N == 0 ? NT : N, NT);
     if (st != IQA_OK) return st;
-    if (kind != IQA_TUNE_SINGLE && kind != IQA_TUNE_BATCH) return IQA_ERR_CONFIG;
+    if (kind != IQA_TUNE_SINGLE && kind != IQA_TUNE_BATCH && kind != IQA_TUNE_SERVE)
+        return IQA_ERR_CONFIG;
     Geometry g{};
     st = geometry(N == 0 ? NT : N, NT, *cfg, g);
     if (st != IQA_OK) return st;
     if (cfg->vec != 4) return IQA_ERR_CONFIG;
-    if (kind == IQA_TUNE_BATCH &&
-        (cfg->waves != 1 || cfg->ksplit != 1 || cfg->unroll != kBatchUnroll))
+    if (kind != IQA_TUNE_SINGLE &&
+        ((cfg->waves != 1 && cfg->waves != kBatchWaves) || cfg->ksplit != 1 ||
+         cfg->unroll != kBatchUnroll))
         return IQA_ERR_CONFIG;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tuned[std::make_tuple(N, NT, kind)] = *cfg;
@@ -1185,8 +1241,24 @@ iqa_status iqa_batch_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg) {
     return IQA_OK;
 }
 
+iqa_status iqa_serve_cfg(int64_t N, int64_t NT, iqa_launch_cfg *cfg) {
+    if (!cfg) return IQA_ERR_NULL;
+    iqa_status st = check_shape(N, NT);
+    if (st != IQA_OK) return st;
+    if (NT % 4 != 0) return IQA_ERR_CONFIG;
+    *cfg = serve_cfg(N, NT);
+    return IQA_OK;
+}
+
 iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
                               int64_t *total_units) {
+    return iqa::describe_pairs(pairs, count, descs, total_units, IQA_TUNE_BATCH);
+}
+
+}  // extern "C"
+
+iqa_status iqa::describe_pairs(const iqa_pair *pairs, int64_t count, void *descs,
+                               int64_t *total_units, int kind) {
     if (!pairs || !descs || !total_units) return IQA_ERR_NULL;
     if (count < 1 || count > INT_MAX) return IQA_ERR_SHAPE;
     BatchDesc *out = static_cast<BatchDesc *>(descs);
@@ -1199,7 +1271,7 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
         if (st != IQA_OK) return st;
         if (p.NT % 4 != 0) return IQA_ERR_CONFIG;
         if (!aligned(p.x, 16) || !aligned(p.y, 16)) return IQA_ERR_ALIGN;
-        const iqa_launch_cfg c = batch_cfg(p.N, p.NT);
+        const iqa_launch_cfg c = kind == IQA_TUNE_SERVE ? serve_cfg(p.N, p.NT) : batch_cfg(p.N, p.NT);
         Geometry g{};
         st = geometry(p.N, p.NT, c, g);
         if (st != IQA_OK) return st;
@@ -1211,13 +1283,15 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
                   p.lisi || p.sums ? p.C1 : 1.f, p.lisi || p.sums ? p.C2 : 1.f,
                   p.auglisi || p.sums ? p.C : 1.f, p.lisi, p.auglisi, p.sums, c, g);
         d.unit_begin = units;
-        units += g.groups;
+        units += batch_units(d.a);
         std::memcpy(out + i, &d, sizeof(d));
     }
     if (units > ((int64_t)1 << 40)) return IQA_ERR_SHAPE;
     *total_units = units;
     return IQA_OK;
 }
+
+extern "C" {
 
 iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
                              int64_t waves, void *stream) {
@@ -1226,8 +1300,7 @@ iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total
     if (!aligned(descs_dev, 16)) return IQA_ERR_ALIGN;
     if (waves < kBatchWaves || waves % kBatchWaves != 0 || waves / kBatchWaves > INT_MAX)
         return IQA_ERR_CONFIG;
-    const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
-                                             (total_units + kBatchWaves - 1) / kBatchWaves);
+    const int64_t blocks = std::min<int64_t>(waves / kBatchWaves, total_units);
     return hip_status(launch_kernel(&batch_kernel<kBatchUnroll>, (unsigned)blocks,
                                     kBatchWaves * kWave, static_cast<hipStream_t>(stream),
                                     static_cast<const BatchDesc *>(descs_dev), (int)count,
@@ -1247,11 +1320,10 @@ iqa_status iqa_tiles_batched_inline(const void *descs_host, int64_t count, int64
         BatchDesc d;
         std::memcpy(&d, static_cast<const BatchDesc *>(descs_host) + i, sizeof(d));
         if (d.unit_begin != next || d.a.ns < 1 || d.a.ngx < 1) return IQA_ERR_CONFIG;
-        next += (int64_t)d.a.ns * d.a.ngx;
+        next += batch_units(d.a);
     }
     if (next != total_units) return IQA_ERR_CONFIG;
-    const int64_t blocks = std::min<int64_t>(waves / kBatchWaves,
-                                             (total_units + kBatchWaves - 1) / kBatchWaves);
+    const int64_t blocks = std::min<int64_t>(waves / kBatchWaves, total_units);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     if (count == 1) return launch_inline<1>(descs_host, count, total_units, blocks, s);
     if (count <= 4) return launch_inline<4>(descs_host, count, total_units, blocks, s);

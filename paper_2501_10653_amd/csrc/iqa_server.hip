@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "iqa.h"
+#include "iqa_internal.h"
 
 namespace iqa_srv {
 
@@ -183,7 +184,8 @@ bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
                             r.lisi, r.auglisi, r.sums};
     }
     int64_t units = 0;
-    if (ok && iqa_batch_describe(pairs.data(), (int64_t)pairs.size(), s.desc_host, &units) != IQA_OK)
+    if (ok && iqa::describe_pairs(pairs.data(), (int64_t)pairs.size(), s.desc_host, &units,
+                                  IQA_TUNE_SERVE) != IQA_OK)
         ok = false;
     // Small batches carry their descriptors in the kernel arguments (one
     // enqueue); larger ones copy the table to the slot's device buffer first.

@@ -19,8 +19,16 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Completion, Request, ServerOpts, ServerStats
+from ._lib import Completion, LaunchCfg, Request, ServerOpts, ServerStats
 from .iqa import C_DEFAULT, default_D
+
+
+def serve_cfg(N: int, NT: int) -> dict:
+    """Per-pair geometry the server uses for (N, NT): a served request's
+    results are bitwise ``iqa_tiles(..., cfg=serve_cfg(N, NT))``."""
+    c = LaunchCfg()
+    _lib.check(_lib.load().iqa_serve_cfg(N, NT, ctypes.byref(c)), "iqa_serve_cfg")
+    return c.as_dict()
 
 
 class ServedRequest:

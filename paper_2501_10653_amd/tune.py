@@ -169,11 +169,14 @@ def tune_single(N: int, NT: int, pool_bytes: float = 2 ** 30, K: int = 64,
 
 
 def candidates_batch(NT: int) -> List[dict]:
+    """Per-pair batch geometries: one wave per tile group (waves 1) or the
+    four waves of a workgroup splitting each tile group's rows (waves 4), at
+    every row-phase count a wave allows."""
     lpt = NT // 4
     seg = min(64, 1 << (lpt - 1).bit_length())
     tpw = 64 // seg
-    return [dict(vec=4, waves=1, unroll=8, seg=seg, rp=1 << r, ksplit=1)
-            for r in range(7) if (1 << r) <= tpw]
+    return [dict(vec=4, waves=w, unroll=8, seg=seg, rp=1 << r, ksplit=1)
+            for w in (1, 4) for r in range(7) if (1 << r) <= tpw]
 
 
 def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 1024, 2048, 4096),
@@ -241,6 +244,58 @@ def tune_batch(NTs: Sequence[int] = (32, 64, 128), Ns: Sequence[int] = (512, 102
     return best, best_w, log_rows
 
 
+SERVE_SHAPES = [(N, NT) for N in (512, 1024, 2048, 4096) for NT in (32, 64, 128)]
+
+
+def tune_serve(shapes: Sequence[Tuple[int, int]] = tuple(SERVE_SHAPES), K: int = 64,
+               refine: int = 3, rounds: int = 3, log=None) -> Tuple[Dict[str, dict], list]:
+    """Per-(N, N_T) geometry for the server's batches, chosen for latency:
+    the time of a batch that holds one pair (as a server's batches mostly
+    do), in graph replays over distinct copies; the fastest few are then
+    re-timed in longer graphs over interleaved rounds."""
+    import torch
+    from . import _lib, synth
+    from ._lib import LaunchCfg
+    from .batch import Batch
+    dev = torch.device("cuda", 0)
+    s = torch.cuda.Stream(dev)
+    timer = _Timer(torch, s)
+    lib = _lib.load()
+    best: Dict[str, dict] = {}
+    log_rows = []
+    for N in sorted({N for N, _ in shapes}):
+        x, y, _ = synth.make_pair(synth.spec_sweep(N, 64))
+        n = max(4, min(64, int(math.ceil((1 << 30) / (8 * N * N)))))
+        xs = device_copies(torch, dev, x, n)
+        ys = device_copies(torch, dev, y, n)
+        for NT in sorted({nt for n2, nt in shapes if n2 == N}):
+            def timed(cfg, K):
+                # the geometry is timed through the batch table; only the
+                # geometry matters to the kernel, not which table holds it
+                _lib.check(lib.iqa_tune_set(N, NT, _lib.TUNE_BATCH, LaunchCfg.from_dict(cfg)),
+                           "iqa_tune_set")
+                bs = [Batch([(xs[i], ys[i], NT)]) for i in range(n)]
+                evict_infinity_cache(torch, dev)
+                us = timer.per_launch_us(lambda i: bs[i % n].run(stream=s), K)
+                lib.iqa_tune_clear()
+                return us
+            res = sorted((timed(c, K), i, c) for i, c in enumerate(candidates_batch(NT)))
+            top = [c for _, _, c in res[:refine]]
+            again = {i: [] for i in range(len(top))}
+            for _ in range(rounds):
+                for i, c in enumerate(top):
+                    again[i].append(timed(c, 4 * K))
+            med = sorted((float(np.median(again[i])), i) for i in range(len(top)))
+            us, i = med[0]
+            best[f"{N}x{NT}"] = top[i]
+            log_rows.append({"N": N, "NT": NT, "cfg": top[i], "us": round(us, 3),
+                             "first_pass": [{"cfg": c, "us": round(u, 3)} for u, _, c in res]})
+            if log:
+                log(f"  serve {N}/{NT}: {us:.2f} us {top[i]}")
+        del xs, ys
+    return best, log_rows
+
+
 def load(path: str = DEFAULT_OUT) -> Optional[dict]:
     if not os.path.exists(path):
         return None
@@ -253,6 +308,7 @@ def main(argv=None) -> int:
     ap.add_argument("--shapes", default="", help="comma list of N:NT")
     ap.add_argument("--sweep", action="store_true", help="the N x N_T size-sweep grid")
     ap.add_argument("--batch", action="store_true", help="tune ragged-batch geometry")
+    ap.add_argument("--serve", action="store_true", help="tune the server's (lone-pair) geometry")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--K", type=int, default=64)
     args = ap.parse_args(argv)
@@ -284,6 +340,10 @@ def main(argv=None) -> int:
         doc["batch"] = {str(NT): cfg for NT, cfg in best.items()}
         doc["batch_waves"] = waves
         doc["batch_log"] = rows
+    if args.serve:
+        best, rows = tune_serve(log=log)
+        doc["serve"] = best
+        doc["serve_log"] = rows
     doc["tuned_at_s"] = round(time.time() - t0, 1)
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     with open(args.out, "w") as fh:

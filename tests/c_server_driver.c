@@ -1,7 +1,7 @@
 /* Drives the serving ABI from plain C, with no Python and no torch: one
  * resident reference, a set of device snapshots, one request per snapshot,
  * then drain, poll and a bitwise comparison of every served result with the
- * single-pair launch of the same geometry (iqa_batch_cfg + iqa_tiles_cfg).
+ * single-pair launch of the same geometry (iqa_serve_cfg + iqa_tiles_cfg).
  * Test infrastructure, built by the build step with a C compiler and run by
  * tests/test_gpu_c_driver.py.
  *
@@ -125,9 +125,9 @@ int main(int argc, char **argv) {
     }
     if (sv) iqa_server_destroy(sv);
 
-    /* The same pairs as single launches with the batch geometry. */
+    /* The same pairs as single launches with the server's geometry. */
     iqa_launch_cfg cfg;
-    int same = iqa_batch_cfg(N, NT, &cfg) == IQA_OK;
+    int same = iqa_serve_cfg(N, NT, &cfg) == IQA_OK;
     for (int64_t i = 0; same && i < count; ++i)
         same = iqa_tiles_cfg(snaps + (size_t)i * npix, ref, N, NT, d, c, c, c,
                              lisi1 + (size_t)i * nt, aug1 + (size_t)i * nt, NULL, &cfg,

@@ -145,11 +145,13 @@ def test_batch_describe_validates_every_pair(over, status):
     st = _lib.load().iqa_batch_describe(arr, 3, buf.ctypes.data, ctypes.byref(units))
     assert st == status
     if status == OK:
-        # one unit per tile group: 8 rows of tiles x ceil(8 / tiles-per-wave)
+        # tile groups: 8 rows of tiles x ceil(8 / tiles-per-wave); a unit is
+        # four groups (one wave each) or one group (four waves splitting rows)
         c = LaunchCfg()
         assert _lib.load().iqa_batch_cfg(256, 32, ctypes.byref(c)) == OK
         ht = 64 // (c.seg * c.rp)
-        assert units.value == 3 * 8 * -(-8 // ht)
+        groups = 8 * -(-8 // ht)
+        assert units.value == 3 * (groups if c.waves == 4 else -(-groups // 4))
 
 
 def test_batch_launch_validation():
@@ -215,8 +217,18 @@ def test_tune_registry():
         wide = LaunchCfg.from_dict(dict(vec=4, waves=1, unroll=8, seg=16, rp=4, ksplit=1))
         assert lib.iqa_tune_set(0, 64, _lib.TUNE_BATCH, ctypes.byref(wide)) == OK
         assert lib.iqa_batch_cfg(4096, 64, ctypes.byref(c2)) == OK and c2.as_dict() == wide.as_dict()
+        # the server's geometry: its own entries, else the batch geometry
+        c3 = LaunchCfg()
+        assert lib.iqa_serve_cfg(4096, 64, ctypes.byref(c3)) == OK and c3.as_dict() == wide.as_dict()
+        coop = LaunchCfg.from_dict(dict(vec=4, waves=4, unroll=8, seg=16, rp=2, ksplit=1))
+        assert lib.iqa_tune_set(1024, 64, _lib.TUNE_SERVE, ctypes.byref(coop)) == OK
+        assert lib.iqa_serve_cfg(1024, 64, ctypes.byref(c3)) == OK and c3.as_dict() == coop.as_dict()
+        assert lib.iqa_batch_cfg(1024, 64, ctypes.byref(c2)) == OK and c2.as_dict() == wide.as_dict()
+        assert lib.iqa_serve_cfg(1024, 62, ctypes.byref(c3)) == SHAPE
+        assert lib.iqa_serve_cfg(1000, 20, ctypes.byref(c3)) == OK
         bad = LaunchCfg.from_dict(dict(vec=4, waves=2, unroll=8, seg=16, rp=2, ksplit=1))
         assert lib.iqa_tune_set(2048, 64, _lib.TUNE_BATCH, ctypes.byref(bad)) == CONFIG
+        assert lib.iqa_tune_set(2048, 64, _lib.TUNE_SERVE, ctypes.byref(bad)) == CONFIG
         assert lib.iqa_tune_set(2048, 64, 7, ctypes.byref(good)) == CONFIG
         assert lib.iqa_tune_set(2048, 63, 0, ctypes.byref(good)) == SHAPE
     finally:

@@ -139,6 +139,45 @@ def test_inline_argument_sizes_equal_device_table(ragged, k):
         assert same(r0.lisi, r1.lisi) and same(r0.auglisi, r1.auglisi) and same(r0.sums, r1.sums)
 
 
+@pytest.mark.parametrize("rp", [1, 2, 4])
+def test_four_wave_geometry_matches_single_launch_and_oracle(ragged, rp):
+    """Pairs whose batch geometry has the four waves of a workgroup split each
+    tile group's rows: bitwise the single-pair launch with that geometry, and
+    within tolerance of the oracle, mixed in one batch with one-wave pairs."""
+    from paper_2501_10653_amd import _lib
+    from paper_2501_10653_amd._lib import LaunchCfg
+    host, dev = ragged
+    lib = _lib.load()
+    coop = set()
+    try:
+        for (x, y, NT) in host:
+            N = x.shape[0]
+            if NT % 4 or (N, NT) in coop or len(coop) >= 6:
+                continue
+            lpt = NT // 4
+            seg = min(64, 1 << (lpt - 1).bit_length())
+            if seg * rp > 64 or NT % 4:
+                continue
+            cfg = dict(vec=4, waves=4, unroll=8, seg=seg, rp=rp, ksplit=1)
+            assert lib.iqa_tune_set(N, NT, _lib.TUNE_BATCH, LaunchCfg.from_dict(cfg)) == 0
+            coop.add((N, NT))
+        assert coop
+        b = Batch(dev, sums=True)
+        b.run()
+        torch.cuda.synchronize()
+        for (x, y, NT), (xd, yd, _), res in zip(host, dev, b.results):
+            N = x.shape[0]
+            if (N, NT) in coop:
+                assert batch_cfg(N, NT)["waves"] == 4
+            single = iqa_tiles(xd, yd, NT, sums=True, cfg=batch_cfg(N, NT))
+            torch.cuda.synchronize()
+            assert same(res.lisi, single.lisi) and same(res.auglisi, single.auglisi), (N, NT)
+            assert same(res.sums, single.sums), (N, NT)
+            assert_parity(res, oracle_for(x, y, NT), what=f"{N}/{NT} rp {rp}")
+    finally:
+        lib.iqa_tune_clear()
+
+
 def test_units_outside_the_table_are_skipped(ragged):
     """A table launch told of more units than described, and of fewer pairs
     than the table holds: the units past the pairs it was given are skipped.

@@ -22,7 +22,7 @@ import torch
 
 from paper_2501_10653_amd import iqa_tiles, synth
 from paper_2501_10653_amd.batch import Batch, batch_cfg
-from paper_2501_10653_amd.serve import Server
+from paper_2501_10653_amd.serve import Server, serve_cfg
 from tests.gpu_util import assert_parity, oracle_for, requires_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
@@ -89,7 +89,7 @@ def test_serving_full_config():
     for (r, NT), req in zip(plan, reqs):
         if (r, NT) not in singles:
             N = specs[r].N
-            singles[(r, NT)] = iqa_tiles(snaps[r][1], refs[r][1], NT, cfg=batch_cfg(N, NT))
+            singles[(r, NT)] = iqa_tiles(snaps[r][1], refs[r][1], NT, cfg=serve_cfg(N, NT))
             torch.cuda.synchronize()
         one = singles[(r, NT)]
         assert same(one.lisi, req.lisi) and same(one.auglisi, req.auglisi), (r, NT)

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_readme_example_runs():
     from paper_2501_10653_amd import iqa_tiles
-    from paper_2501_10653_amd.batch import batch_cfg
+    from paper_2501_10653_amd.serve import serve_cfg
     text = open(os.path.join(ROOT, "README.md")).read()
     code = re.search(r"```python\n(.*?)```", text, re.S).group(1)
     ns = {}
@@ -30,7 +30,7 @@ def test_readme_example_runs():
     done = ns["done"]
     assert len(done) == 1 and done[0]["status"] == 0
     req, x, y = ns["req"], ns["x"], ns["y"]
-    single = iqa_tiles(y, x, 64, cfg=batch_cfg(2048, 64))
+    single = iqa_tiles(y, x, 64, cfg=serve_cfg(2048, 64))
     torch.cuda.synchronize()
     assert torch.equal(req.lisi.view(torch.int32), single.lisi.view(torch.int32))
     assert torch.equal(req.auglisi.view(torch.int32), single.auglisi.view(torch.int32))

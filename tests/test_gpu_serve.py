@@ -10,8 +10,7 @@ import pytest
 import torch
 
 from paper_2501_10653_amd import iqa_tiles, synth
-from paper_2501_10653_amd.batch import batch_cfg
-from paper_2501_10653_amd.serve import Server, latency_summary
+from paper_2501_10653_amd.serve import Server, latency_summary, serve_cfg
 from tests.gpu_util import assert_parity, oracle_for, requires_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
@@ -61,7 +60,7 @@ def test_alone_equals_mix_equals_single_launch(world):
         alone_srv.close()
         assert same(alone.lisi, req.lisi) and same(alone.auglisi, req.auglisi)
         N = refs[r][1].shape[0]
-        single = iqa_tiles(snaps[r][k][1], refs[r][1], NT, cfg=batch_cfg(N, NT))
+        single = iqa_tiles(snaps[r][k][1], refs[r][1], NT, cfg=serve_cfg(N, NT))
         torch.cuda.synchronize()
         assert same(single.lisi, req.lisi) and same(single.auglisi, req.auglisi)
 

@@ -29,9 +29,11 @@ def test_batch_candidates_follow_the_batch_rules(NT):
     cands = tune.candidates_batch(NT)
     assert cands
     for c in cands:
-        # batch geometry: vec 4, one wave per tile group, no row split, unroll 8
-        assert (c["vec"], c["waves"], c["ksplit"], c["unroll"]) == (4, 1, 1, 8)
+        # batch geometry: vec 4, one wave per tile group or four splitting its
+        # rows, no split across workgroups, unroll 8
+        assert (c["vec"], c["ksplit"], c["unroll"]) == (4, 1, 8) and c["waves"] in (1, 4)
         assert check_cfg(4096, NT, c) == 0, c
+    assert {c["waves"] for c in cands} == {1, 4}
 
 
 def test_tuned_table_matches_the_json_cache(tmp_path):
@@ -39,17 +41,19 @@ def test_tuned_table_matches_the_json_cache(tmp_path):
         "single": {"2048x64": {"cfg": dict(vec=4, waves=4, unroll=8, seg=16, rp=2, ksplit=1)},
                    "1024x256": {"cfg": dict(vec=4, waves=4, unroll=8, seg=64, rp=1, ksplit=8)}},
         "batch": {"64": dict(vec=4, waves=1, unroll=8, seg=16, rp=2, ksplit=1)},
+        "serve": {"1024x64": dict(vec=4, waves=4, unroll=8, seg=16, rp=2, ksplit=1)},
         "batch_waves": 4096,
     }
     src = tmp_path / "cache.json"
     src.write_text(json.dumps(doc))
     inc = tmp_path / "table.inc"
-    assert build.write_tuned_table(str(src), str(inc)) == 3
+    assert build.write_tuned_table(str(src), str(inc)) == 4
     text = inc.read_text()
     assert "{1024, 256, 0, {4, 4, 8, 64, 1, 8}}," in text
     assert "{2048, 64, 0, {4, 4, 8, 16, 2, 1}}," in text
     assert "{0, 64, 1, {4, 1, 8, 16, 2, 1}}," in text
-    assert "kTunedCount = 3;" in text and "kTunedBatchWaves = 4096;" in text
+    assert "{1024, 64, 2, {4, 4, 8, 16, 2, 1}}," in text
+    assert "kTunedCount = 4;" in text and "kTunedBatchWaves = 4096;" in text
     # no cache: an empty table that still compiles
     empty = tmp_path / "empty.inc"
     assert build.write_tuned_table(str(tmp_path / "missing.json"), str(empty)) == 0
@@ -64,4 +68,8 @@ def test_committed_cache_entries_are_valid():
         assert check_cfg(N, NT, rec["cfg"]) == 0, key
     for NT, cfg in doc["batch"].items():
         assert check_cfg(4096, int(NT), cfg) == 0, NT
+    for key, cfg in doc.get("serve", {}).items():
+        N, NT = (int(v) for v in key.split("x"))
+        assert check_cfg(N, NT, cfg) == 0, key
+        assert cfg["waves"] in (1, 4) and cfg["ksplit"] == 1 and cfg["unroll"] == 8, key
     assert doc["batch_waves"] >= 4 and doc["batch_waves"] % 4 == 0
