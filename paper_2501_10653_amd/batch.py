@@ -59,12 +59,27 @@ class Batch:
         self.results: List[TileResult] = []
         self.bytes = 0
         batched, self.single = [], []      # pairs the persistent kernel takes / does not
-        for i, (x, y, NT) in enumerate(pairs):
+        # Every output is a view into one buffer (each array at a 16-byte
+        # aligned offset): one allocation, and one stream record per run.
+        sizes = []
+        for x, y, NT in pairs:
             N = _check_images(x, y)
             ns = N // NT if NT > 0 and N % NT == 0 else 0
-            lo = torch.empty(ns, ns, device=self.device)
-            ao = torch.empty(ns, ns, device=self.device)
-            so = torch.empty(ns * ns, 4, device=self.device) if sums else None
+            sizes.append(ns)
+        pad = lambda n: (n + 3) // 4 * 4
+        per = [2 * pad(ns * ns) + (pad(4 * ns * ns) if sums else 0) for ns in sizes]
+        self.out = torch.empty(max(1, sum(per)), device=self.device)
+        off = 0
+        for i, ((x, y, NT), ns) in enumerate(zip(pairs, sizes)):
+            N = x.shape[0]
+            lo = self.out[off:off + ns * ns].view(ns, ns)
+            off += pad(ns * ns)
+            ao = self.out[off:off + ns * ns].view(ns, ns)
+            off += pad(ns * ns)
+            so = None
+            if sums:
+                so = self.out[off:off + 4 * ns * ns].view(ns * ns, 4)
+                off += pad(4 * ns * ns)
             self.inputs.append((x, y, NT))
             self.results.append(TileResult(lo, ao, so))
             self.bytes += 8 * N * N
@@ -114,10 +129,6 @@ class Batch:
                                                    self.waves,
                                                    _stream_handle(self.device, stream))
                 _lib.check(st, "iqa_tiles_batched")
-            if self.count:
-                # the outputs and the descriptor table were allocated on torch's
-                # current stream; the launch may run on another torch stream
-                _mark_used(stream, self.descs, *(t for r in self.results for t in r))
             for i in self.single:
                 x, y, NT = self.inputs[i]
                 r = self.results[i]
@@ -126,6 +137,9 @@ class Batch:
                     out["sums"] = r.sums
                 iqa_tiles(x, y, NT, sums=r.sums is not None, out=out, stream=stream,
                           **self.consts)
+            # the outputs and the descriptor table were allocated on torch's
+            # current stream; the launches may run on another torch stream
+            _mark_used(stream, self.descs, self.out)
 
     def capture(self, stream: Optional[torch.cuda.Stream] = None) -> torch.cuda.CUDAGraph:
         """Capture one run into a HIP graph; replay it with ``graph.replay()``

@@ -219,7 +219,7 @@ def test_tune_registry():
         assert lib.iqa_batch_cfg(4096, 64, ctypes.byref(c2)) == OK and c2.as_dict() == wide.as_dict()
         # the server's geometry: its own entries, else the batch geometry
         c3 = LaunchCfg()
-        assert lib.iqa_serve_cfg(4096, 64, ctypes.byref(c3)) == OK and c3.as_dict() == wide.as_dict()
+        assert lib.iqa_serve_cfg(8192, 64, ctypes.byref(c3)) == OK and c3.as_dict() == wide.as_dict()
         coop = LaunchCfg.from_dict(dict(vec=4, waves=4, unroll=8, seg=16, rp=2, ksplit=1))
         assert lib.iqa_tune_set(1024, 64, _lib.TUNE_SERVE, ctypes.byref(coop)) == OK
         assert lib.iqa_serve_cfg(1024, 64, ctypes.byref(c3)) == OK and c3.as_dict() == coop.as_dict()
