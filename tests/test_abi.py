@@ -199,6 +199,36 @@ def test_inline_batch_checks_the_unit_numbering():
     assert lib.iqa_tiles_batched_inline(swapped.ctypes.data, 3, u, 2048, None) == CONFIG
 
 
+def test_batch_units_follow_each_pairs_geometry():
+    """A unit is one workgroup: four tile groups of a one-wave pair, one tile
+    group of a four-wave pair.  Described totals follow each pair's geometry,
+    and the inline launch accepts exactly that total."""
+    import numpy as np
+    lib = _lib.load()
+    lib.iqa_tune_clear()
+    try:
+        one = LaunchCfg.from_dict(dict(vec=4, waves=1, unroll=8, seg=8, rp=2, ksplit=1))
+        four = LaunchCfg.from_dict(dict(vec=4, waves=4, unroll=8, seg=8, rp=2, ksplit=1))
+        assert lib.iqa_tune_set(256, 32, _lib.TUNE_BATCH, ctypes.byref(one)) == OK
+        assert lib.iqa_tune_set(512, 32, _lib.TUNE_BATCH, ctypes.byref(four)) == OK
+        arr = (_lib.IqaPair * 3)()
+        for i, N in enumerate((256, 512, 256)):
+            arr[i] = _lib.IqaPair(FAKE, FAKE, N, 32, C6 / 2, C6, C6, C6, FAKE, FAKE, None)
+        buf = np.zeros(3 * _lib.BATCH_DESC_BYTES, np.uint8)
+        units = ctypes.c_int64(-1)
+        assert lib.iqa_batch_describe(arr, 3, buf.ctypes.data, ctypes.byref(units)) == OK
+        # seg 8, rp 2: 4 tiles per wave.  256/32: 8 x 2 groups -> 4 units;
+        # 512/32: 16 x 4 groups, each its own unit -> 64 units
+        assert units.value == 4 + 64 + 4
+        begins = [int(np.frombuffer(buf[i * 128 + 120:i * 128 + 128].tobytes(), np.int64)[0])
+                  for i in range(3)]
+        assert begins == [0, 4, 68]
+        for total in (units.value - 1, units.value + 1):
+            assert lib.iqa_tiles_batched_inline(buf.ctypes.data, 3, total, 2048, None) == CONFIG
+    finally:
+        lib.iqa_tune_clear()
+
+
 def test_tune_registry():
     lib = _lib.load()
     lib.iqa_tune_clear()

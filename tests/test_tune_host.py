@@ -73,3 +73,15 @@ def test_committed_cache_entries_are_valid():
         assert check_cfg(N, NT, cfg) == 0, key
         assert cfg["waves"] in (1, 4) and cfg["ksplit"] == 1 and cfg["unroll"] == 8, key
     assert doc["batch_waves"] >= 4 and doc["batch_waves"] % 4 == 0
+
+
+def test_serving_geometry_covers_the_served_shapes():
+    """The compiled-in serving table has an entry for every shape the server's
+    tuner covers, and the Python helper reports what the library uses."""
+    from paper_2501_10653_amd.serve import serve_cfg
+    with open(build.TUNED_JSON) as fh:
+        doc = json.load(fh)
+    for N, NT in tune.SERVE_SHAPES:
+        key = f"{N}x{NT}"
+        assert key in doc.get("serve", {}), key
+        assert serve_cfg(N, NT) == {k: int(v) for k, v in doc["serve"][key].items()}, key
