@@ -262,9 +262,9 @@ iqa_status iqa_batch_describe(const iqa_pair *pairs, int64_t count, void *descs,
  * into a HIP graph.  The descriptor contents are not validated on the device:
  * pass exactly what iqa_batch_describe wrote, and a device buffer that holds
  * at least `count` descriptors.  A unit number that falls outside its pair's
- * tile groups (total_units larger than described, or count smaller) is
- * skipped by the kernel, never read from; tiles of units beyond total_units
- * are left unwritten. */
+ * units (total_units larger than described, or count smaller) is skipped by
+ * the kernel, never read from; tiles of units beyond total_units are left
+ * unwritten. */
 iqa_status iqa_tiles_batched(const void *descs_dev, int64_t count, int64_t total_units,
                              int64_t waves, void *stream);
 
