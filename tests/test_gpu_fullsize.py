@@ -95,3 +95,35 @@ def test_serving_full_config():
         assert same(one.lisi, req.lisi) and same(one.auglisi, req.auglisi), (r, NT)
     for (r, NT), one in singles.items():
         assert_parity(one, oracle_for(snaps[r][0], refs[r][0], NT), what=f"ref {r} NT={NT}")
+
+
+def test_serving_under_overload():
+    """20,000 requests arriving at 100k/s, beyond what the device can serve:
+    batches grow past the inline limit (device descriptor table), slots are
+    reused as fast as their completion words arrive, and every result still
+    equals its single-pair launch bitwise.  N_T 128 is mixed in, so pairs of
+    one- and four-wave geometries share batches."""
+    specs = synth.serving_references(count=16, seed=11)
+    refs, snaps = [], []
+    for sp in specs:
+        x, _, _ = synth.make_pair(sp)
+        refs.append(to_dev(x))
+        snaps.append(to_dev(synth.make_snapshot(sp, 1)))
+    rng = np.random.default_rng(23)
+    plan = [(int(rng.integers(len(specs))), int(rng.choice([32, 64, 128]))) for _ in range(20000)]
+    print(f"overload: {len(plan)} requests at 100k/s", flush=True)
+    with Server(32 << 30, streams=4, max_batch=512) as srv:
+        ids = [srv.add_reference(d) for d in refs]
+        reqs = [srv.request(snaps[r], ids[r], NT) for r, NT in plan]
+        arrivals = synth.poisson_arrivals(100000.0, len(reqs), seed=5)
+        comps = srv.replay(reqs, arrivals, timeout_s=120.0)
+        st = srv.stats()
+    assert len(comps) == len(reqs) and all(c["status"] == 0 for c in comps)
+    assert st["completed"] == len(reqs) and st["max_batch"] > 16
+    singles = {}
+    for (r, NT), req in zip(plan, reqs):
+        if (r, NT) not in singles:
+            singles[(r, NT)] = iqa_tiles(snaps[r], refs[r], NT, cfg=serve_cfg(specs[r].N, NT))
+            torch.cuda.synchronize()
+        one = singles[(r, NT)]
+        assert same(one.lisi, req.lisi) and same(one.auglisi, req.auglisi), (r, NT)
