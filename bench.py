@@ -7,10 +7,25 @@ the paper's shape: N = 2048, N_T = 64 (32 x 32 IQA matrix).  Inputs are
 resident in HBM before the timed region.  Steps rotate over a pool of distinct
 device copies of the pair (>= 1 GiB in total) so that no step is served from
 the 256 MB Infinity Cache that the previous steps filled.  The K timed steps
-are one replay of a HIP graph holding exactly K launches.
+are one replay of a HIP graph holding exactly K launches; before it the
+stream runs a few large fills, so the timed region starts with the K launches
+already queued (the GPU's back-to-back rate, not the host's submission delay).
 
-Prints one JSON line (rank 0).  ``--gpus N`` with N > 1 is not supported: this
-is a single-GPU path.
+The default run also reports, on the same GPU: the fastest plain read of the
+same bytes, the 2 GiB read ceiling, the paper's two separate kernels, a
+same-shape batch, the 256-pair ragged batch (one persistent launch in a graph
+against 256 single-pair launches), serving at 2k, 10k and 50k requests/s
+(throughput, p50 and p99 latency to the caller's poll) and the FP64 oracle on
+the host cores (median of 10 runs per configuration, one thread and all).
+
+Other workloads: ``--workload readfloor`` (plain reads and empty launches of
+the pair's byte count in many shapes), ``timeline`` (per-workgroup timeline of
+the fused launch), ``sweep`` (every cell of the size sweep), ``ragged``,
+``serve``.  ``--plan-out`` writes the launch plan that
+``python -m paper_2501_10653_amd.measure`` matches against a rocprofv3 trace.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 is not supported: this is a
+single-GPU path.
 """
 
 from __future__ import annotations
@@ -32,9 +47,9 @@ if ROOT not in sys.path:
 
 METRIC = "fused LISI+augLISI HBM GB/s (% peak) at 2048²/NT64; p99 request latency"
 HBM_PEAK_GBS = 8000.0       # MI355X published HBM3E bandwidth
-READ_BLOCKS = 1024          # workgroups of the same-size plain read (its fastest measured shape)
 KERNEL_SRC = os.path.join(ROOT, "paper_2501_10653_amd", "csrc", "iqa_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
+SWEEP_CELLS = [(N, NT) for N in (1024, 2048, 4096, 8192) for NT in (16, 32, 64, 128, 256)]
 
 
 def parse_args(argv=None):
@@ -43,26 +58,32 @@ def parse_args(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="paper",
-                    help="paper (2048/64, default), small (256/32), N:NT (sweep recipe) "
-                         "or serve (request-rate sweep)")
+                    help="paper (2048/64, default), small (256/32), N:NT (sweep recipe), "
+                         "readfloor, timeline, sweep, ragged or serve")
     ap.add_argument("--pool-bytes", type=float, default=1.0 * 2 ** 30,
                     help="total bytes of distinct pair copies the steps rotate over")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="wall time of the CPU oracle baseline sample")
+    ap.add_argument("--cpu-runs", type=int, default=10,
+                    help="timed runs of the CPU oracle per configuration (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of a graph")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the side measurements of the default run (the 2 GiB read "
-                         "ceiling, the two separate kernels, the same-shape batch)")
+                    help="skip the side measurements of the default run (read floor and "
+                         "ceiling, separate kernels, batches, serving)")
     ap.add_argument("--profile", action="store_true",
                     help="profiling run: a few eager launches plus a 256 MiB copy of known size")
-    ap.add_argument("--serve-rate", type=float, default=10000.0,
-                    help="Poisson request rate of the serving leg of the default run (0: skip)")
+    ap.add_argument("--serve-rates", default="2000,10000,50000",
+                    help="Poisson request rates of the serving leg of the default run ('' skips)")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--rates", default="2000,5000,10000,20000,50000",
                     help="request rates of --workload serve (device-resident snapshots)")
     ap.add_argument("--h2d-rates", default="500,1000,2000",
                     help="request rates of --workload serve with pinned host snapshots")
+    ap.add_argument("--sweep-launches", type=int, default=200,
+                    help="launches per graph for --workload sweep and readfloor")
+    ap.add_argument("--cells", default="",
+                    help="--workload sweep: N:NT cells to run (default: all 20)")
+    ap.add_argument("--plan-out", default="",
+                    help="write the launch plan (for a rocprofv3 trace summary) to this file")
     return ap.parse_args(argv)
 
 
@@ -95,66 +116,80 @@ def traffic_record(N: int, NT: int, cfg: dict):
     return rec
 
 
-def cpu_baseline(x, y, NT, seconds: float, bytes_pair: int, n_tiles: int,
-                 gpu_lisi: np.ndarray, gpu_aug: np.ndarray) -> dict:
-    """The FP64 oracle, as it stands, on the host cores: repeated over the same
-    pair until ``seconds`` of wall time have passed.  Its output also checks
-    the last timed GPU result (LISI relative error, augLISI error relative to
-    max(|augLISI|, P/(Sx+Sy+C)))."""
+def _oracle_runs(x, y, NT: int, runs: int, threads: Optional[int] = None) -> dict:
+    """`runs` timed calls of the FP64 oracle on one pair (after one untimed
+    call), on `threads` OpenMP threads (None: all); median, min and p90."""
     from oracle import oracle
     c = oracle.f32const(1e-6)
-    ol, oa, _ = oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)       # also warms the caches
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
+    keep = oracle.num_threads()
+    if threads is not None:
+        oracle.set_num_threads(threads)
+    try:
+        used = oracle.num_threads()
         oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
+            ts.append(time.perf_counter() - t0)
+    finally:
+        oracle.set_num_threads(keep)
+    t = np.array(ts)
+    N = x.shape[0]
+    med = float(np.median(t))
+    return {"N": N, "NT": NT, "threads": used, "runs": runs,
+            "median_ms": round(med * 1e3, 4), "min_ms": round(float(t.min()) * 1e3, 4),
+            "p90_ms": round(float(np.percentile(t, 90)) * 1e3, 4),
+            "GBs": round(8 * N * N / med / 1e9, 4),
+            "tiles_per_s": round((N // NT) ** 2 / med, 1)}
+
+
+def cpu_baseline(x, y, NT, runs: int, gpu_lisi: np.ndarray, gpu_aug: np.ndarray) -> dict:
+    """The FP64 oracle, as it stands, timed on the host cores: the median of
+    `runs` runs on the headline pair (all threads, and one thread), then the
+    small configuration (256^2 / 32) and the corners of the size sweep
+    (1024^2 and 8192^2 at N_T 16 and 256; one generated pair per N, since the
+    oracle's time does not depend on the pixel values).  Its output on the
+    headline pair also checks the last timed GPU result (LISI relative error,
+    augLISI error relative to max(|augLISI|, P/(Sx+Sy+C)))."""
+    from oracle import oracle
+    from paper_2501_10653_amd import synth
+    t_all = time.perf_counter()
+    c = oracle.f32const(1e-6)
+    ol, oa, _ = oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
+    head = _oracle_runs(x, y, NT, runs)
+    one = _oracle_runs(x, y, NT, runs, threads=1)
+    configs = [head, one]
+    xs, ys, _ = synth.make_pair(synth.spec_small())
+    configs += [_oracle_runs(xs, ys, 32, runs), _oracle_runs(xs, ys, 32, runs, threads=1)]
+    for N in (1024, 8192):
+        xc, yc, _ = synth.make_pair(synth.spec_sweep(N, 16))
+        for nt in (16, 256):
+            configs += [_oracle_runs(xc, yc, nt, runs), _oracle_runs(xc, yc, nt, runs, threads=1)]
+        del xc, yc
     ol, oa = ol.ravel(), oa.ravel()
     gl = gpu_lisi.astype(np.float64).ravel()
     ga = gpu_aug.astype(np.float64).ravel()
     lisi_rel = np.abs(gl - ol) / np.where(ol != 0, np.abs(ol), 1.0)
     aug_err = np.abs(ga - oa) / np.maximum(np.abs(oa), np.abs(1.0 - oa))
+    N = x.shape[0]
     return {
-        "value": round(bytes_pair * reps / el / 1e9, 4),
+        "value": head["GBs"],
         "unit": "GB/s",
-        "cores": oracle.num_threads(),
+        "cores": head["threads"],
         "kind": "oracle",
-        "tiles_per_s": round(n_tiles * reps / el, 1),
-        "ms_per_pair": round(el / reps * 1e3, 3),
-        "sample": f"FP64 C oracle (OpenMP over tile rows) on the same {x.shape[0]}x{x.shape[0]} "
-                  f"pair, {reps} repetitions in {el:.1f} s",
+        "tiles_per_s": head["tiles_per_s"],
+        "ms_per_pair": head["median_ms"],
+        "sample": f"FP64 C oracle (OpenMP over tile rows), median of {runs} runs on the "
+                  f"{N}x{N} / {NT} pair; single thread and the other configurations in "
+                  f"'configs' ({time.perf_counter() - t_all:.1f} s in all)",
+        "single_thread": one,
+        "configs": configs,
         "parity_of_last_gpu_step": {"lisi_max_rel": float(lisi_rel.max()),
                                     "aug_max_err": float(aug_err.max()),
                                     "pass_1e-5": bool(lisi_rel.max() <= 1e-5
                                                       and aug_err.max() <= 1e-5)},
     }
-
-
-def cpu_single_thread(x, y, NT, seconds: float, bytes_pair: int) -> dict:
-    """The same oracle on one OpenMP thread (per-tile summation order is the
-    same, so its results are bitwise those of the threaded run)."""
-    from oracle import oracle
-    c = oracle.f32const(1e-6)
-    threads = oracle.num_threads()
-    oracle.set_num_threads(1)
-    try:
-        used = oracle.num_threads()
-        oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            oracle.iqa_tiles(x, y, NT, c / 2, c, c, c)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= seconds:
-                break
-    finally:
-        oracle.set_num_threads(threads)
-    return {"value": round(bytes_pair * reps / el / 1e9, 4), "unit": "GB/s", "cores": used,
-            "ms_per_pair": round(el / reps * 1e3, 3),
-            "sample": f"the same pair, {reps} repetitions in {el:.1f} s"}
 
 
 def cpu_model() -> str:
@@ -199,7 +234,9 @@ class ServingWorld:
             r = int(rng.integers(len(self.refs)))
             k = int(rng.integers(len(snaps[r])))
             NT = int(rng.choice([32, 64]))
-            out.append(srv.request(snaps[r][k], ids[r], NT))
+            # every snapshot is complete before the replay starts (run_serving
+            # synchronises the device), so the batches need no ready event
+            out.append(srv.request(snaps[r][k], ids[r], NT, ready=False))
             nbytes += 8 * self.specs[r].N ** 2
         return out, nbytes
 
@@ -222,6 +259,7 @@ def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 3
     with Server(budget, streams=streams, max_batch=max_batch, host_arena_bytes=arena) as srv:
         ids = [srv.add_reference(r) for r in world.refs]
         reqs, nbytes = world.requests(srv, ids, count, seed, host=host)
+        torch.cuda.synchronize()
         arrivals = synth.poisson_arrivals(rate, count, seed=seed)
         comps = srv.replay(reqs, arrivals, timeout_s=120.0)
         st = srv.stats()
@@ -232,7 +270,8 @@ def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 3
                  "peak_in_flight_MiB": round(st["peak_in_flight_bytes"] / 2 ** 20, 1),
                  "budget_GiB": budget / 2 ** 30, "streams": streams,
                  "GBs_delivered": round(nbytes * summ.get("throughput_rps", 0) / count / 1e9, 1)})
-    for k in ("p50_us", "p99_us", "max_us", "mean_us", "throughput_rps", "span_s"):
+    for k in ("p50_us", "p99_us", "max_us", "mean_us", "p50_done_us", "p99_done_us",
+              "throughput_rps", "span_s"):
         if k in summ:
             summ[k] = round(summ[k], 2)
     return summ
@@ -257,8 +296,6 @@ def ragged_pairs(torch, dev, count: int = 256, seed: int = 7):
         x, y = proto[(sp.N, 1 if sp.n_drop else 0)]
         pairs.append((x.clone(), y.clone(), sp.NT))
     del proto
-    from paper_2501_10653_amd.tune import evict_infinity_cache
-    evict_infinity_cache(torch, dev)
     return pairs
 
 
@@ -267,21 +304,26 @@ def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
     and N_T over {32, 64, 128}, 20% with 1-5 faintest sources removed and the
     rest noise-only.  One prototype pair is generated per (N, kind) and copied
     into distinct device buffers for every pair (timing is content-independent).
-    Times one persistent launch (eager and graph-replayed) against `count`
-    single-pair launches (eager and graph-replayed)."""
+    Times one persistent launch (eager, and in a graph) against `count`
+    single-pair launches with their tuned shapes (eager, and in a graph), each
+    the median of 5 timed runs after a prelude."""
     from paper_2501_10653_amd import iqa_tiles
     from paper_2501_10653_amd.batch import Batch
+    from paper_2501_10653_amd.measure import GraphTimer
     pairs = ragged_pairs(torch, dev, count, seed)
     total = sum(8 * p[0].shape[0] ** 2 for p in pairs)
     s = torch.cuda.Stream(dev)
+    timer = GraphTimer(torch, dev, s)
 
-    def timeit(fn, reps=5):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+    def eager_ms(fn, reps=5):
         fn()
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         ts = []
         for _ in range(reps):
+            torch.cuda.synchronize()
+            timer.run_prelude(1e-3)
             e0.record(s)
             fn()
             e1.record(s)
@@ -291,15 +333,9 @@ def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
 
     b = Batch(pairs)
     out = {"pairs": count, "bytes": total, "units": b.units, "waves": b.waves}
-    ms = timeit(lambda: b.run(stream=s))
-    out["batched_eager_ms"] = round(ms, 4)
+    out["batched_eager_ms"] = round(eager_ms(lambda: b.run(stream=s)), 4)
     g = b.capture(s)
-
-    def replay(graph):
-        with torch.cuda.stream(s):
-            graph.replay()
-
-    ms = timeit(lambda: replay(g))
+    ms = float(np.median(timer.replay_ms(g, reps=5)))
     out["batched_graph_ms"] = round(ms, 4)
     out["batched_graph_GBs"] = round(total / ms / 1e6, 1)
     outs = [(torch.empty(p[0].shape[0] // p[2], p[0].shape[0] // p[2], device=dev),
@@ -310,17 +346,130 @@ def run_ragged(torch, dev, count: int = 256, seed: int = 7) -> dict:
         for (x, y, NT), (lo, ao) in zip(pairs, outs):
             iqa_tiles(x, y, NT, out={"lisi": lo, "auglisi": ao}, stream=s)
 
-    ms = timeit(plain)
+    ms = eager_ms(plain)
     out["plain_eager_ms"] = round(ms, 4)
     out["plain_eager_GBs"] = round(total / ms / 1e6, 1)
     g2 = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g2, stream=s):
         plain()
-    ms = timeit(lambda: replay(g2))
+    ms = float(np.median(timer.replay_ms(g2, reps=5)))
     out["plain_graph_ms"] = round(ms, 4)
     out["plain_graph_GBs"] = round(total / ms / 1e6, 1)
     out["hbm_frac_batched"] = round(out["batched_graph_GBs"] / HBM_PEAK_GBS, 4)
+    out["batched_vs_plain_graph"] = round(out["plain_graph_ms"] / out["batched_graph_ms"], 3)
+    del g, g2, b, pairs
+    torch.cuda.empty_cache()
     return out
+
+
+def run_readfloor(torch, dev, args) -> dict:
+    """Plain reads and empty launches of the headline pair's byte count, in
+    many shapes, beside the fused kernel timed the same way."""
+    from paper_2501_10653_amd import default_cfg, iqa_tiles, synth
+    from paper_2501_10653_amd.measure import GraphTimer, Plan, read_floor
+    from paper_2501_10653_amd.tune import device_copies
+    plan = Plan()
+    spec = workload_spec("paper" if args.workload == "readfloor" else args.workload)
+    N, NT = spec.N, spec.NT
+    nbytes = 8 * N * N
+    K = args.sweep_launches
+    floor = read_floor(torch, dev, nbytes, K=K, pool_bytes=args.pool_bytes, plan=plan)
+    x, y, _ = synth.make_pair(spec)
+    pool = max(2, int(math.ceil(args.pool_bytes / nbytes)))
+    xs = device_copies(torch, dev, x, pool)
+    ys = device_copies(torch, dev, y, pool)
+    stream = torch.cuda.Stream(dev)
+    timer = GraphTimer(torch, dev, stream)
+    cfg = default_cfg(N, NT, xs[0], ys[0])
+    ns = N // NT
+    out = {"lisi": torch.empty(ns, ns, device=dev), "auglisi": torch.empty(ns, ns, device=dev)}
+    us = timer.per_launch_us(lambda i: iqa_tiles(xs[i % pool], ys[i % pool], NT, out=out,
+                                                 cfg=cfg, stream=stream), K)
+    plan.add(f"fused {N}^2/{NT} (warm)", "tiles_kernel", K, bytes=nbytes)
+    plan.add(f"fused {N}^2/{NT}", "tiles_kernel", K, bytes=nbytes)
+    if args.plan_out:
+        plan.dump(args.plan_out)
+    best = floor["fastest_read"]
+    return {"metric": f"plain-read floor of one {nbytes}-byte launch", "unit": "us",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": f"{nbytes} B per launch (a {N}^2 FP32 pair), "
+                                   f"{K} launches per graph over {floor['pool_buffers']} "
+                                   f"distinct buffers"},
+            "fused": {"cfg": cfg, "us": round(us, 3), "GBs": round(nbytes / us / 1e3, 1),
+                      "vs_fastest_read": round(best["us"] / us, 4)},
+            "fastest_read": best, "fastest_empty": floor["fastest_empty"],
+            "rows": floor["rows"]}
+
+
+def run_timeline(torch, dev, args) -> dict:
+    from paper_2501_10653_amd import default_cfg, synth
+    from paper_2501_10653_amd.measure import timeline
+    from paper_2501_10653_amd.tune import device_copies
+    spec = workload_spec("paper" if args.workload == "timeline" else args.workload)
+    x, y, _ = synth.make_pair(spec)
+    nbytes = 8 * spec.N ** 2
+    pool = max(2, int(math.ceil(args.pool_bytes / nbytes)))
+    xs = device_copies(torch, dev, x, pool)
+    ys = device_copies(torch, dev, y, pool)
+    cfg = default_cfg(spec.N, spec.NT, xs[0], ys[0])
+    res = timeline(torch, dev, xs, ys, spec.NT, cfg, launches=64)
+    return {"metric": "per-workgroup timeline of the fused launch", "unit": "us",
+            "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": f"{spec.N}^2 / {spec.NT}, 64 back-to-back launches in a "
+                                   f"graph over {pool} distinct pairs"},
+            "timeline": res}
+
+
+def run_sweep(torch, dev, args) -> dict:
+    """Every cell of the size sweep (N in 1024..8192, N_T in 16..256) with its
+    default launch shape, K launches per graph over >= 1 GiB of distinct
+    copies, timed with events (median of 3 replays)."""
+    from paper_2501_10653_amd import default_cfg, iqa_tiles, synth
+    from paper_2501_10653_amd.measure import GraphTimer, Plan
+    from paper_2501_10653_amd.tune import device_copies
+    plan = Plan()
+    cells = SWEEP_CELLS
+    if args.cells:
+        cells = [tuple(int(v) for v in c.split(":")) for c in args.cells.split(",")]
+    K = args.sweep_launches
+    stream = torch.cuda.Stream(dev)
+    timer = GraphTimer(torch, dev, stream)
+    rows = []
+    pairs = {}
+    for N, NT in cells:
+        if N not in pairs:
+            pairs.clear()
+            torch.cuda.empty_cache()
+            x, y, _ = synth.make_pair(synth.spec_sweep(N, 64))
+            pool = max(2, int(math.ceil(args.pool_bytes / (8 * N * N))))
+            pairs[N] = (device_copies(torch, dev, x, pool), device_copies(torch, dev, y, pool))
+        xs, ys = pairs[N]
+        pool = len(xs)
+        cfg = default_cfg(N, NT, xs[0], ys[0])
+        ns = N // NT
+        out = {"lisi": torch.empty(ns, ns, device=dev),
+               "auglisi": torch.empty(ns, ns, device=dev)}
+        g = timer.capture(lambda i: iqa_tiles(xs[i % pool], ys[i % pool], NT, out=out, cfg=cfg,
+                                              stream=stream), K)
+        ms = timer.replay_ms(g, reps=3)
+        del g
+        us = float(np.median(ms)) * 1e3 / K
+        nbytes = 8 * N * N
+        plan.add(f"{N}^2/{NT} (warm)", "tiles_kernel", K, bytes=nbytes)
+        for r in range(3):
+            plan.add(f"{N}^2/{NT}" + ("" if r == 0 else f" (rep {r + 1})"), "tiles_kernel", K,
+                     bytes=nbytes)
+        rows.append({"N": N, "NT": NT, "cfg": cfg, "us": round(us, 3),
+                     "GBs": round(nbytes / us / 1e3, 1),
+                     "frac_of_peak": round(nbytes / us / 1e3 / HBM_PEAK_GBS, 4)})
+        print(json.dumps({"cell": f"{N}x{NT}", "us": round(us, 3)}), file=sys.stderr, flush=True)
+    if args.plan_out:
+        plan.dump(args.plan_out)
+    return {"metric": "fused kernel time per size-sweep cell", "unit": "us",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": f"size sweep, {K} launches per graph per cell, distinct "
+                                   f"copies >= {args.pool_bytes / 2 ** 30:.0f} GiB"},
+            "cells": rows}
 
 
 def main(argv=None) -> int:
@@ -334,13 +483,19 @@ def main(argv=None) -> int:
     import torch
     from paper_2501_10653_amd import default_cfg, iqa_tiles, synth
     from paper_2501_10653_amd.iqa import auglisi_tiles, lisi_tiles, read_ceiling
-    from paper_2501_10653_amd.tune import device_copies, evict_infinity_cache
+    from paper_2501_10653_amd.measure import GraphTimer
+    from paper_2501_10653_amd.tune import device_copies
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no HIP device visible"}))
         return 1
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    special = {"readfloor": run_readfloor, "timeline": run_timeline, "sweep": run_sweep}
+    if args.workload in special:
+        print(json.dumps(special[args.workload](torch, dev, args)), flush=True)
+        return 0
 
     if args.workload == "ragged" and args.profile:
         # Counter runs: three eager launches of the batch, then a copy of known
@@ -394,7 +549,6 @@ def main(argv=None) -> int:
     pool = max(2, int(math.ceil(args.pool_bytes / bytes_pair)))
     xs = device_copies(torch, dev, x, pool)
     ys = device_copies(torch, dev, y, pool)
-    evict_infinity_cache(torch, dev)
     lisi = torch.empty(ns, ns, device=dev)
     aug = torch.empty(ns, ns, device=dev)
     out = {"lisi": lisi, "auglisi": aug}
@@ -427,20 +581,21 @@ def main(argv=None) -> int:
 
     K = args.steps
     use_graph = not args.no_graph
-    graph = None
-    if use_graph:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
-            for i in range(K):
-                step(i)
-        torch.cuda.synchronize()
-        with torch.cuda.stream(stream):
-            graph.replay()                  # one untimed replay
-        torch.cuda.synchronize()
-
+    timer = GraphTimer(torch, dev, stream)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    if use_graph:
+        graph = timer.capture(step, K)
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            graph.replay()                  # one untimed replay
+        host_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+    else:
+        host_s = 1e-3
+    # The timed region: K launches already queued behind the prelude.
     torch.cuda.synchronize()
+    timer.run_prelude(host_s)
     wall0 = time.perf_counter()
     t_start.record(stream)
     if use_graph:
@@ -462,10 +617,12 @@ def main(argv=None) -> int:
 
     gpu_lisi = lisi.cpu().numpy()
     gpu_aug = aug.cpu().numpy()
-    reference = same_size_read(torch, dev, bytes_pair, pool, stream, read_ceiling, K)
+    if use_graph:
+        del graph
 
-    extras, batched = {}, None
+    extras, batched, floor = {}, None, None
     if not args.no_extras:
+        floor = quick_read_floor(torch, dev, bytes_pair, args.pool_bytes)
         extras = run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling,
                             lisi_tiles, auglisi_tiles, iqa_tiles, cfg, bytes_pair)
         extras["kernel_frac_of_read_ceiling"] = round(gbs / extras["read_ceiling_gbs"], 4)
@@ -505,88 +662,59 @@ def main(argv=None) -> int:
         "hbm_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
         "wall_s_timed": round(wall, 4),
         "roofline": roofline,
-        "reference_read": {**reference,
-                           "kernel_frac_of_plain_read":
-                               round(reference["us_per_launch"] / (ms_step * 1e3), 4)},
     }
+    if floor:
+        line["reference_read"] = {**floor,
+                                  "kernel_frac_of_fastest_read":
+                                      round(floor["fastest_read"]["us"] / (ms_step * 1e3), 4)}
     if extras:
         line["extras"] = extras
     if batched:
         line["batched"] = batched
-    if args.serve_rate > 0 and args.workload == "paper":
-        del xs, ys
-        torch.cuda.empty_cache()
+    del xs, ys
+    torch.cuda.empty_cache()
+    if not args.no_extras and args.workload == "paper":
+        line["ragged"] = run_ragged(torch, dev)
+    if args.serve_rates and not args.no_extras and args.workload == "paper":
         world = ServingWorld(torch, dev)
-        line["serving"] = run_serving(torch, world, args.serve_rate, args.serve_seconds)
+        line["serving"] = [run_serving(torch, world, float(r), args.serve_seconds, seed=i)
+                           for i, r in enumerate(args.serve_rates.split(","))]
+        del world
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(x, y, NT, args.cpu_seconds, bytes_pair, ns * ns,
-                                            gpu_lisi, gpu_aug)
+        line["cpu_baseline"] = cpu_baseline(x, y, NT, args.cpu_runs, gpu_lisi, gpu_aug)
         line["cpu_baseline"]["cpu_model"] = cpu_model()
-        line["cpu_baseline"]["single_thread"] = cpu_single_thread(
-            x, y, NT, min(5.0, args.cpu_seconds), bytes_pair)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
     return 0
 
 
-def same_size_read(torch, dev, nbytes: int, pool: int, stream, read_ceiling, K: int) -> dict:
-    """A plain float4 read of the same number of bytes per launch, over a pool
-    of distinct buffers and timed the same way (K launches in one graph):
-    what a launch of this size can reach on this GPU."""
-    from paper_2501_10653_amd.tune import evict_infinity_cache
-    bufs = [torch.empty(nbytes // 4, device=dev) for _ in range(pool)]
-    for b in bufs:
-        b.fill_(1.0)
-    evict_infinity_cache(torch, dev)
-    out = torch.empty(READ_BLOCKS, device=dev)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=stream):
-        for i in range(K):
-            read_ceiling(bufs[i % pool], out, stream=stream)
-    with torch.cuda.stream(stream):
-        g.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    with torch.cuda.stream(stream):
-        g.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    us = e0.elapsed_time(e1) / K * 1e3
-    del g, bufs
-    torch.cuda.empty_cache()
-    return {"us_per_launch": round(us, 3), "gbs": round(nbytes / us / 1e3, 1),
-            "workgroups": READ_BLOCKS, "loads": "non-temporal float4"}
+def quick_read_floor(torch, dev, nbytes: int, pool_bytes: float) -> dict:
+    """A few shapes of the plain read of the same bytes per launch (the ones
+    that came out fastest in the full read-floor sweep), timed like the
+    headline: what a launch of this size can reach on this GPU."""
+    from paper_2501_10653_amd.measure import read_floor
+    res = read_floor(torch, dev, nbytes, K=200, pool_bytes=pool_bytes, quick=True)
+    return {"fastest_read": res["fastest_read"], "fastest_empty": res["fastest_empty"],
+            "shapes_timed": len(res["rows"])}
 
 
 def run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling, lisi_tiles,
                auglisi_tiles, iqa_tiles, cfg, bytes_pair) -> dict:
-    """Read ceiling over >= 2 GiB, and the two separate kernels vs the fused one."""
+    """Read ceiling over 2 GiB, and the two separate kernels vs the fused one."""
+    from paper_2501_10653_amd.measure import GraphTimer
     ex = {}
+    timer = GraphTimer(torch, dev, stream)
     buf = torch.empty(512 * 2 ** 20, device=dev)      # 2 GiB
     buf.fill_(1.0)
     outc = torch.empty(8192, device=dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        for _ in range(3):
-            read_ceiling(buf, outc, stream=stream)
-        best = []
-        for _ in range(5):
-            ev0.record(stream)
-            read_ceiling(buf, outc, stream=stream)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            best.append(ev0.elapsed_time(ev1))
-    ms = min(best)
-    ex["read_ceiling_gbs"] = round(buf.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    us = timer.per_launch_us(lambda i: read_ceiling(buf, outc, stream=stream), 5, reps=3)
+    ex["read_ceiling_gbs"] = round(buf.numel() * 4 / us / 1e3, 1)
     del buf
-
     ns = N // NT
     lo = torch.empty(ns, ns, device=dev)
     ao = torch.empty(ns, ns, device=dev)
-    from paper_2501_10653_amd.tune import evict_infinity_cache
-    evict_infinity_cache(torch, dev)
     K = 400
     for name, fn in (("lisi_only", lambda i: lisi_tiles(xs[i % pool], ys[i % pool], NT, out=lo,
                                                          stream=stream)),
@@ -595,21 +723,9 @@ def run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling, lisi_tiles
                      ("fused", lambda i: iqa_tiles(xs[i % pool], ys[i % pool], NT,
                                                    out={"lisi": lo, "auglisi": ao}, cfg=cfg,
                                                    stream=stream))):
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
-            for i in range(K):
-                fn(i)
-        with torch.cuda.stream(stream):
-            g.replay()
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        with torch.cuda.stream(stream):
-            g.replay()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / K
-        ex[f"{name}_us"] = round(ms * 1e3, 3)
-        ex[f"{name}_gbs"] = round(bytes_pair / (ms * 1e-3) / 1e9, 1)
+        us = timer.per_launch_us(fn, K)
+        ex[f"{name}_us"] = round(us, 3)
+        ex[f"{name}_gbs"] = round(bytes_pair / us / 1e3, 1)
     ex["separate_total_us"] = round(ex["lisi_only_us"] + ex["auglisi_only_us"], 3)
     return ex
 
@@ -620,23 +736,11 @@ def run_same_shape_batch(torch, xs, ys, NT, stream, bytes_pair, single_ms, reps:
     throughput of the same pairs when they come as a batch rather than one
     launch each, next to the single-launch value."""
     from paper_2501_10653_amd.batch import Batch
-    from paper_2501_10653_amd.tune import evict_infinity_cache
+    from paper_2501_10653_amd.measure import GraphTimer
     b = Batch([(x, y, NT) for x, y in zip(xs, ys)])
-    evict_infinity_cache(torch, xs[0].device)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=stream):
-        for _ in range(reps):
-            b.run(stream=stream)
-    with torch.cuda.stream(stream):
-        g.replay()
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    with torch.cuda.stream(stream):
-        g.replay()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
+    timer = GraphTimer(torch, xs[0].device, stream)
+    us_launch = timer.per_launch_us(lambda i: b.run(stream=stream), reps)
+    ms = us_launch / 1e3
     ns = xs[0].shape[0] // NT
     gbs = len(xs) * (bytes_pair + 2 * 4 * ns * ns) / (ms * 1e-3) / 1e9
     out = {"pairs_per_launch": len(xs), "launches": reps, "waves": b.waves,
@@ -644,7 +748,7 @@ def run_same_shape_batch(torch, xs, ys, NT, stream, bytes_pair, single_ms, reps:
            "us_per_pair": round(ms * 1e3 / len(xs), 3),
            "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
            "vs_single_launch": round(single_ms / (ms / len(xs)), 3)}
-    del g, b
+    del b
     return out
 
 

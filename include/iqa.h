@@ -33,14 +33,24 @@
  *   Calls on the same stream are ordered; calls on different streams may run
  *   concurrently.
  * Scratch.  Shapes with few, large tiles split a tile's rows over several
- *   workgroups whose partial sums a second, small kernel combines on the same
- *   stream; those launches use a small library-owned device workspace per
- *   (device, stream) (16 bytes per tile and split part), allocated on first
- *   use and reused afterwards (an outgrown buffer is kept until the process
- *   ends, so graphs captured earlier stay valid).  The first call for a given
- *   (device, stream, shape) must therefore not happen while the stream is
- *   being captured into a graph: call iqa_prepare() (or the entry point
- *   itself) once before.
+ *   workgroups of one launch; each stores its partial sums and the last one
+ *   of a tile to finish adds them in a fixed order and writes the tile's
+ *   results (a ticket counter decides which is last; nothing waits).  Those
+ *   launches use a small library-owned device workspace per (device, stream)
+ *   (16 bytes per tile and split part, plus 4 bytes per tile group),
+ *   allocated and cleared on first use and reused afterwards (an outgrown
+ *   buffer is kept until the process ends, so graphs captured earlier stay
+ *   valid).  The first call for a given (device, stream, shape) must
+ *   therefore not happen while the stream is being captured into a graph:
+ *   call iqa_prepare() (or the entry point itself) once before.
+ * Threads.  Every entry point may be called from several host threads at
+ *   once, on the same stream or on different ones.  Calls on one stream run
+ *   in the order they were enqueued, each launch finishing before the next
+ *   starts, so split launches on one stream share its workspace safely.  A
+ *   HIP graph that captured a split-shape launch keeps the capture stream's
+ *   workspace: replay it on that stream (or on one stream at a time, with
+ *   nothing else using that workspace meanwhile), because two split launches
+ *   running at the same time on one workspace would mix their partial sums.
  * Errors.  Every entry point validates its arguments before touching the GPU
  *   and returns a status; nothing is launched when the status is not IQA_OK.
  *   Launch failures are reported as IQA_ERR_HIP, with the HIP error code
@@ -124,8 +134,8 @@ iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT,
  * row in `vec`-float loads and `rp` such segments take interleaved rows, so a
  * wave covers ht = 64/(seg*rp) adjacent tiles and reduces them without LDS.
  * A workgroup of `waves` waves splits those tiles' rows into contiguous
- * slices (combined in LDS); `ksplit` workgroups split them further (combined
- * by a second kernel on the same stream).  `unroll` rows per lane are loaded
+ * slices (combined in LDS); `ksplit` workgroups split them further (the last
+ * of them to finish combines their partial sums).  `unroll` rows per lane are loaded
  * while the previous `unroll` are reduced. */
 typedef struct iqa_launch_cfg {
     int32_t vec;     /* floats per lane load: 4, 2 or 1; NT % vec == 0 */
@@ -152,6 +162,10 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT,
                          float D, float C1, float C2, float C,
                          float *lisi, float *auglisi, float *sums,
                          const iqa_launch_cfg *cfg, void *stream);
+
+/* Workgroups of the single-pair launch for (N, NT) with `cfg` (one per tile
+ * group and split part); -1 if the shape or configuration is invalid. */
+int64_t iqa_launch_workgroups(int64_t N, int64_t NT, const iqa_launch_cfg *cfg);
 
 /* Allocate, ahead of time, the workspace that (N, NT) with `cfg` (NULL =
  * default) needs on `stream`, so that later calls allocate nothing (e.g.
@@ -321,6 +335,17 @@ typedef struct iqa_server_opts {
                                   at once; polling occupies one CPU core) */
 } iqa_server_opts;
 
+/* Ordering with the caller's own work.  The server runs each batch on its
+ * own streams, which are not ordered after any stream of the caller.  A
+ * snapshot or an output buffer that work on a caller's stream still writes
+ * or reads (a snapshot produced by a kernel, an output buffer a caching
+ * allocator just handed out) therefore needs `ready_event`: a hipEvent_t
+ * recorded on that stream after that work.  The batch that carries the
+ * request waits for it on the device (hipStreamWaitEvent) before it reads
+ * the snapshot or writes the outputs.  The event must stay valid until the
+ * request completes.  With ready_event NULL the caller guarantees that the
+ * snapshot is complete and the outputs are unused when it submits (e.g. after
+ * synchronising the producing stream). */
 typedef struct iqa_request {
     const float *snapshot_dev;   /* device N x N snapshot (16-byte aligned), or NULL */
     const float *snapshot_host;  /* pinned host snapshot, or NULL; exactly one is set */
@@ -331,6 +356,7 @@ typedef struct iqa_request {
     int32_t ref_id;              /* from iqa_server_add_reference */
     int32_t reserved;
     uint64_t tag;                /* returned in the completion */
+    void *ready_event;           /* hipEvent_t the request's batch waits for, or NULL */
 } iqa_request;
 
 typedef struct iqa_completion {
@@ -338,9 +364,10 @@ typedef struct iqa_completion {
     int32_t status;              /* IQA_OK, or why the request was rejected / failed */
     int32_t reserved;
     int64_t t_submit_ns;         /* steady-clock times: submitted, admitted, */
-    int64_t t_admit_ns;          /* launched, and seen complete by the scheduler */
-    int64_t t_launch_ns;
+    int64_t t_admit_ns;          /* launched, seen complete by the scheduler, */
+    int64_t t_launch_ns;         /* and handed to the caller by iqa_server_poll */
     int64_t t_done_ns;
+    int64_t t_poll_ns;
 } iqa_completion;
 
 typedef struct iqa_server_stats {
@@ -407,6 +434,53 @@ iqa_status iqa_server_destroy(iqa_server *sv);
  * that the tile kernels are compared with; the sums carry no meaning. */
 iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blocks,
                             void *stream);
+
+/* iqa_tiles_cfg with a per-workgroup timeline, for measuring where a launch's
+ * time goes (vec 4 configurations only, else IQA_ERR_CONFIG).  The results
+ * are those of iqa_tiles_cfg with the same configuration, bitwise.
+ *   stamps       device, stamp_count uint64 (8-byte aligned), at least
+ *                8 * iqa_launch_workgroups(N, NT, cfg) (else IQA_ERR_SHAPE).
+ *                Workgroup b (in launch order) writes stamps[8b .. 8b+7]:
+ *                wall-clock ticks (see hipDeviceAttributeWallClockRate) of its
+ *                first wave's entry, of its first batch of rows reduced (its
+ *                first loads back), of its last rows reduced (its last loads
+ *                back) and of its exit once its results were stored; then the
+ *                XCC_ID and HW_ID hardware registers it ran with, its tile
+ *                group and split part.
+ * The stamps cost a few instructions per workgroup; the product entry points
+ * are separate kernels without them. */
+iqa_status iqa_tiles_timeline(const float *x, const float *y, int64_t N, int64_t NT, float D,
+                              float C1, float C2, float C, float *lisi, float *auglisi,
+                              float *sums, const iqa_launch_cfg *cfg, uint64_t *stamps,
+                              int64_t stamp_count, void *stream);
+
+/* Measurement probes (they compute nothing the library returns).
+ * iqa_probe_empty: one launch of an empty kernel, `blocks` workgroups of
+ *   `threads` (1..1024) threads: the fixed cost of a launch.
+ * iqa_probe_read: a plain read of the n floats at `buf` (device, 16-byte
+ *   aligned, n % 4 == 0) by `blocks` workgroups of `threads` threads (a
+ *   multiple of 64, at most 1024), each summing a contiguous share with
+ *   `loads` (4, 8, 16 or 32) 16-byte loads in flight per lane, and writing
+ *   one float to `out` (device, `blocks` floats).  `mode`:
+ *     IQA_PROBE_READ_REGS         loads into registers, kernel arguments
+ *                                 preloaded into SGPRs at wave start;
+ *     IQA_PROBE_READ_REGS_STRUCT  the same, arguments loaded from memory;
+ *     IQA_PROBE_READ_LDS          loads straight into LDS (16 bytes per
+ *                                 lane per load, loads * threads * 16 bytes
+ *                                 of LDS, at most 64 KiB, else
+ *                                 IQA_ERR_CONFIG).
+ * The HIP error behind an IQA_ERR_HIP is iqa_probe_last_hip_error(). */
+#define IQA_PROBE_READ_REGS 0
+#define IQA_PROBE_READ_REGS_STRUCT 1
+#define IQA_PROBE_READ_LDS 2
+iqa_status iqa_probe_empty(int64_t blocks, int32_t threads, void *stream);
+iqa_status iqa_probe_read(const float *buf, int64_t n, float *out, int64_t blocks,
+                          int32_t threads, int32_t loads, int32_t mode, void *stream);
+int iqa_probe_last_hip_error(void);
+
+/* Rate of the device wall clock that iqa_tiles_timeline's stamps count, in
+ * kHz, for the current device (-1 if it cannot be read). */
+int64_t iqa_wall_clock_khz(void);
 
 /* Static, human-readable name of a status code. */
 const char *iqa_status_str(int status);

@@ -60,7 +60,8 @@ class Request(ctypes.Structure):
     _fields_ = [("snapshot_dev", ctypes.c_void_p), ("snapshot_host", ctypes.c_void_p),
                 ("lisi", ctypes.c_void_p), ("auglisi", ctypes.c_void_p),
                 ("sums", ctypes.c_void_p), ("NT", ctypes.c_int64), ("ref_id", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tag", ctypes.c_uint64)]
+                ("reserved", ctypes.c_int32), ("tag", ctypes.c_uint64),
+                ("ready_event", ctypes.c_void_p)]
 
 
 class Completion(ctypes.Structure):
@@ -69,7 +70,7 @@ class Completion(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64),
                 ("t_admit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
-                ("t_done_ns", ctypes.c_int64)]
+                ("t_done_ns", ctypes.c_int64), ("t_poll_ns", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -87,6 +88,9 @@ BATCH_INLINE_MAX = 16
 TUNE_SINGLE = 0
 TUNE_BATCH = 1
 TUNE_SERVE = 2
+PROBE_READ_REGS = 0
+PROBE_READ_REGS_STRUCT = 1
+PROBE_READ_LDS = 2
 
 
 class IqaError(RuntimeError):
@@ -130,6 +134,14 @@ def load() -> ctypes.CDLL:
         "iqa_check_cfg": ([i64, i64, cfgp], ctypes.c_int),
         "iqa_tiles_cfg": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp], ctypes.c_int),
         "iqa_prepare": ([i64, i64, cfgp, vp], ctypes.c_int),
+        "iqa_launch_workgroups": ([i64, i64, cfgp], i64),
+        "iqa_tiles_timeline": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp, i64, vp],
+                               ctypes.c_int),
+        "iqa_probe_empty": ([i64, ctypes.c_int32, vp], ctypes.c_int),
+        "iqa_probe_read": ([vp, i64, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp],
+                           ctypes.c_int),
+        "iqa_probe_last_hip_error": ([], ctypes.c_int),
+        "iqa_wall_clock_khz": ([], i64),
         "iqa_read_ceiling": ([vp, i64, vp, i64, vp], ctypes.c_int),
         "iqa_merge_tiles": ([vp, i64, i64, f, f, f, vp, vp, vp, vp], ctypes.c_int),
         "iqa_tune_set": ([i64, i64, ctypes.c_int, cfgp], ctypes.c_int),

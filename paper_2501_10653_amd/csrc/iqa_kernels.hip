@@ -15,8 +15,9 @@
 //     adjacent tiles, and a whole tile slice reduces inside one wave with DPP
 //     lane permutations, with no LDS and no barrier.  Several waves of a
 //     workgroup may share a tile's rows (combined once in LDS), and for shapes
-//     with few large tiles several workgroups share them (combined by a second,
-//     tiny kernel that runs after the first on the same stream).
+//     with few large tiles several workgroups share them (the last of them to
+//     finish combines their partials, chosen by an atomic ticket; no second
+//     launch).
 //   * Each lane folds `vec` adjacent pixels with plain FP32 (FMA chains) and
 //     adds the block into Kahan-compensated (hi, lo) accumulators: the long
 //     per-lane sums are compensated.  Across lanes the partial sums are folded
@@ -338,6 +339,19 @@ __device__ __forceinline__ int udiv(int n, uint32_t m, int d) {
 }
 
 // ---------------------------------------------------------------------------
+// Timeline stamps (diagnostic launches only)
+// ---------------------------------------------------------------------------
+//
+// The constant-rate wall clock, read once `v` has been computed: the empty
+// volatile asm needs v in a register, and volatile statements keep their
+// order with the clock read, so the stamp cannot move above the arithmetic
+// (and the loads) that produced v.
+__device__ __forceinline__ uint64_t stamp_after(float v) {
+    asm volatile("" ::"v"(v));
+    return wall_clock64();
+}
+
+// ---------------------------------------------------------------------------
 // One wave's slice of one tile group
 // ---------------------------------------------------------------------------
 //
@@ -347,8 +361,9 @@ __device__ __forceinline__ int udiv(int n, uint32_t m, int d) {
 // tile j = L >> log_grp, row phase k = (L >> log_seg) & (rp-1) and column
 // group l = L & (seg-1): rows k, k+rp, k+2rp, ... of the slice.  Returns the
 // slice's sums of tile j, the same on every lane of the tile's lane group.
-template <int VEC, int U, int MODE, bool WIDE>
-__device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int slice, int lane) {
+template <int VEC, int U, int MODE, bool WIDE, bool TL = false>
+__device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int slice, int lane,
+                                           uint64_t *ts = nullptr) {
     using V = typename VecT<VEC>::T;
     const int seg = 1 << a.log_seg;
     const int log_rp = a.log_grp - a.log_seg;
@@ -402,6 +417,9 @@ __device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int 
 #pragma unroll
                     for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(ax[u], ay[u], a.C1, b);
                     add_block<MODE>(acc, b);
+                    if constexpr (TL) {
+                        if (m == 0) ts[0] = stamp_after(acc.X.hi);
+                    }
                 }
                 m += U;
                 if (!more_c) break;
@@ -432,6 +450,9 @@ __device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int 
             Sum4 b{0.f, 0.f, 0.f, 0.f};
             accumulate<VEC, MODE>(xv, yv, a.C1, b);
             add_block<MODE>(acc, b);
+            if constexpr (TL) {
+                if (m == 0) ts[0] = stamp_after(acc.X.hi);
+            }
         }
     } else {
         // Tile rows wider than a segment: chunk q covers column group l + q*seg.
@@ -456,9 +477,13 @@ __device__ __forceinline__ Sum4 slice_sums(const KArgs &a, int ty, int txg, int 
 #pragma unroll
                 for (int u = 0; u < U; ++u) accumulate<VEC, MODE>(xv[u], yv[u], a.C1, b);
                 add_block<MODE>(acc, b);
+                if constexpr (TL) {
+                    if (m == 0 && q0 == 0) ts[0] = stamp_after(acc.X.hi);
+                }
             }
         }
     }
+    if constexpr (TL) ts[1] = stamp_after(acc.X.hi);
 
     // Sum the lanes of each tile inside the wave.
     return group_allreduce<MODE>(fold(acc), a.log_grp);
@@ -482,14 +507,69 @@ __device__ __forceinline__ float4 wave_tree(float4 (&v)[WAVES]) {
 }
 
 // ---------------------------------------------------------------------------
+// Split tiles: the last part to arrive finishes the tile group
+// ---------------------------------------------------------------------------
+//
+// With ks > 1 workgroups per tile group, every part stores its partial sums
+// (one float4 per tile) and then takes a ticket from the group's counter.
+// The part that draws the last ticket has seen, through the counter's
+// release/acquire chain at agent scope, every other part's partials: it adds
+// them in part order (Kahan-compensated, the same order whichever part comes
+// last, so results are bitwise reproducible), finalises, and sets the counter
+// back to zero for the next launch.  No part waits for another.
+//
+// Workspace layout: partials [group][part][ht] float4, then one 32-bit
+// counter per group.  Counters start at zero and every launch leaves them at
+// zero.
+__host__ __device__ __forceinline__ int64_t split_partials(int64_t groups, int64_t ks, int64_t ht) {
+    return groups * ks * ht;   // float4 entries
+}
+
+template <int MODE>
+__device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, int lane,
+                                             bool mine, int jt, int64_t t, float4 v) {
+    float4 *ws = reinterpret_cast<float4 *>(a.ws);
+    const int64_t base = (int64_t)grp * a.ks;
+    if (mine) ws[(base + part) * a.ht + jt] = v;
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(
+                        ws + split_partials((int64_t)a.ns * a.ngx, a.ks, a.ht)) + grp;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    uint32_t ticket = 0;
+    if (lane == 0) ticket = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    if (ticket != (uint32_t)(a.ks - 1)) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (mine) {
+        Acc c = acc_zero();
+        for (int p = 0; p < a.ks; ++p) {
+            const float4 w = ws[(base + p) * a.ht + jt];
+            if constexpr ((MODE & kLisi) != 0) cadd(c.A, w.x);
+            if constexpr ((MODE & kAug) != 0) cadd(c.P, w.y);
+            cadd(c.X, w.z);
+            cadd(c.Y, w.w);
+        }
+        finalize<MODE>(a, t, c);
+    }
+    if (lane == 0) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
 // The tile kernel (one image pair)
 // ---------------------------------------------------------------------------
 //
 // Grid: one workgroup of WAVES waves per (tile group, split part).  The tile
 // rows are cut into WAVES*ks contiguous slices of rows_wave rows; wave w of
 // part p takes slice p*WAVES + w.
-template <int VEC, int WAVES, int U, int MODE, bool WIDE>
-__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
+//
+// TL (diagnostic launches only) records, per workgroup, wall-clock stamps of
+// wave 0: entry, its first batch of rows reduced (first loads back), its last
+// rows reduced (last loads back), and its exit after the results are stored,
+// plus the XCD and hardware slot it ran on: 8 uint64 per workgroup at
+// tl[8 * blockIdx.x], written with ordinary vector stores.
+template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool TL>
+__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a, uint64_t *tl) {
+    uint64_t ts[4] = {0, 0, 0, 0};
+    if constexpr (TL) ts[0] = wall_clock64();
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -497,36 +577,53 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
     const int part = bid - grp * a.ks;
     const int ty = udiv(grp, a.ngx_m, a.ngx);
     const int txg = grp - ty * a.ngx;
-    const int j = lane >> a.log_grp;
-    const int tx = txg * a.ht + j;
 
-    const Sum4 s = slice_sums<VEC, U, MODE, WIDE>(a, ty, txg, part * WAVES + wave, lane);
-    const bool leader = (lane & ((1 << a.log_grp) - 1)) == 0;
+    const Sum4 s = slice_sums<VEC, U, MODE, WIDE, TL>(a, ty, txg, part * WAVES + wave, lane, ts + 1);
 
+    // The tile this lane finishes, if any: a lane group's leader with one wave
+    // per workgroup; lane j of wave 0 after the LDS combine otherwise.
+    bool mine;
+    int jt;
+    float4 v{s.A, s.P, s.X, s.Y};
     if constexpr (WAVES == 1) {
-        if (!leader || tx >= a.ns) return;
-        if (a.ks == 1) {
-            finalize<MODE>(a, (int64_t)ty * a.ns + tx, acc_of(s));
-        } else {
-            float4 v{s.A, s.P, s.X, s.Y};
-            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + j] = v;
-        }
+        jt = lane >> a.log_grp;
+        mine = (lane & ((1 << a.log_grp) - 1)) == 0 && txg * a.ht + jt < a.ns;
     } else {
         // Combine the waves' slices of each tile in LDS, wave order fixed.
         __shared__ float4 lds[WAVES][kWave];
-        if (leader) lds[wave][j] = float4{s.A, s.P, s.X, s.Y};
+        if ((lane & ((1 << a.log_grp) - 1)) == 0) lds[wave][lane >> a.log_grp] = v;
         __syncthreads();
-        if (wave != 0 || lane >= a.ht) return;
-        const int txl = txg * a.ht + lane;
-        if (txl >= a.ns) return;
-        float4 v[WAVES];
+        if (wave != 0) return;
+        jt = lane;
+        mine = lane < a.ht && txg * a.ht + lane < a.ns;
+        if (mine) {
+            float4 w[WAVES];
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) v[w] = lds[w][lane];
-        const float4 t = wave_tree<WAVES>(v);
-        if (a.ks == 1) {
-            finalize<MODE>(a, (int64_t)ty * a.ns + txl, acc_of(Sum4{t.x, t.y, t.z, t.w}));
-        } else {
-            reinterpret_cast<float4 *>(a.ws)[((int64_t)grp * a.ks + part) * a.ht + lane] = t;
+            for (int i = 0; i < WAVES; ++i) w[i] = lds[i][lane];
+            v = wave_tree<WAVES>(w);
+        }
+    }
+    const int64_t t = (int64_t)ty * a.ns + txg * a.ht + jt;
+    if (a.ks == 1) {
+        if (mine) finalize<MODE>(a, t, acc_of(Sum4{v.x, v.y, v.z, v.w}));
+    } else {
+        split_finish<MODE>(a, grp, part, lane, mine, jt, t, v);
+    }
+    if constexpr (TL) {
+        if (wave == 0) {
+            __builtin_amdgcn_s_waitcnt(0);   // every store of the wave has landed
+            const uint64_t t_end = wall_clock64();
+            if (lane == 0) {
+                uint64_t *r = tl + (int64_t)blockIdx.x * 8;
+                r[0] = ts[0];
+                r[1] = ts[1];
+                r[2] = ts[2];
+                r[3] = t_end;
+                r[4] = (uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 20);   // XCC_ID
+                r[5] = (uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
+                r[6] = (uint64_t)grp;
+                r[7] = (uint64_t)part;
+            }
         }
     }
 }
@@ -639,30 +736,6 @@ struct InlineDescs {
 template <int U, int CAP>
 __global__ __launch_bounds__(kBatchWaves * kWave) void batch_kernel_inline(InlineDescs<CAP> in) {
     batch_body<U>(in.d, in.count, in.units);
-}
-
-// Split tiles: one thread per tile adds the ks parts' partial sums in part
-// order and finalises.  Runs after tiles_kernel on the same stream, so the
-// partials are complete and visible.
-template <int MODE>
-__global__ __launch_bounds__(256) void combine_kernel(KArgs a) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t n = (int64_t)a.ns * a.ns;
-    if (t >= n) return;
-    const int64_t ty = t / a.ns;
-    const int64_t tx = t - ty * a.ns;
-    const int64_t grp = ty * a.ngx + tx / a.ht;
-    const int64_t j = tx % a.ht;
-    Acc c = acc_zero();
-    const float4 *ws = reinterpret_cast<const float4 *>(a.ws);
-    for (int p = 0; p < a.ks; ++p) {
-        const float4 v = ws[(grp * a.ks + p) * a.ht + j];
-        if constexpr ((MODE & kLisi) != 0) cadd(c.A, v.x);
-        if constexpr ((MODE & kAug) != 0) cadd(c.P, v.y);
-        cadd(c.X, v.z);
-        cadd(c.Y, v.w);
-    }
-    finalize<MODE>(a, t, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,19 +854,20 @@ iqa_status hip_status(hipError_t e) {
     return IQA_ERR_HIP;
 }
 
-using LaunchFn = hipError_t (*)(const KArgs &, unsigned, hipStream_t);
+using LaunchFn = hipError_t (*)(const KArgs &, uint64_t *, unsigned, hipStream_t);
 
-template <int VEC, int WAVES, int U, int MODE, bool WIDE>
-hipError_t launch_impl(const KArgs &a, unsigned grid, hipStream_t s) {
-    return launch_kernel(&tiles_kernel<VEC, WAVES, U, MODE, WIDE>, grid, WAVES * kWave, s, a);
+template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool TL>
+hipError_t launch_impl(const KArgs &a, uint64_t *tl, unsigned grid, hipStream_t s) {
+    return launch_kernel(&tiles_kernel<VEC, WAVES, U, MODE, WIDE, TL>, grid, WAVES * kWave, s, a,
+                         tl);
 }
 
 template <int VEC, int WAVES, int U, bool WIDE>
 LaunchFn pick_mode(int mode) {
     switch (mode) {
-        case kLisi: return &launch_impl<VEC, WAVES, U, kLisi, WIDE>;
-        case kAug: return &launch_impl<VEC, WAVES, U, kAug, WIDE>;
-        default: return &launch_impl<VEC, WAVES, U, kBoth, WIDE>;
+        case kLisi: return &launch_impl<VEC, WAVES, U, kLisi, WIDE, false>;
+        case kAug: return &launch_impl<VEC, WAVES, U, kAug, WIDE, false>;
+        default: return &launch_impl<VEC, WAVES, U, kBoth, WIDE, false>;
     }
 }
 
@@ -831,13 +905,26 @@ LaunchFn pick(const iqa_launch_cfg &c, int mode, bool wide) {
     return nullptr;
 }
 
-hipError_t launch_combine(const KArgs &a, int mode, hipStream_t s) {
-    const int64_t n = (int64_t)a.ns * a.ns;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    void (*fn)(KArgs) = mode == kLisi  ? &combine_kernel<kLisi>
-                        : mode == kAug ? &combine_kernel<kAug>
-                                       : &combine_kernel<kBoth>;
-    return launch_kernel(fn, blocks, 256, s, a);
+// Timeline launches (diagnostics): the fused kernel with stamps, for the vec 4
+// shapes.
+template <int WAVES, int U>
+LaunchFn pick_tl_wide(bool wide) {
+    return wide ? &launch_impl<4, WAVES, U, kBoth, true, true>
+                : &launch_impl<4, WAVES, U, kBoth, false, true>;
+}
+
+LaunchFn pick_tl(const iqa_launch_cfg &c, bool wide) {
+    if (c.vec != 4) return nullptr;
+    const bool u8 = c.unroll == 8;
+    if (c.unroll != 4 && c.unroll != 8) return nullptr;
+    switch (c.waves) {
+        case 1: return u8 ? pick_tl_wide<1, 8>(wide) : pick_tl_wide<1, 4>(wide);
+        case 2: return u8 ? pick_tl_wide<2, 8>(wide) : pick_tl_wide<2, 4>(wide);
+        case 4: return u8 ? pick_tl_wide<4, 8>(wide) : pick_tl_wide<4, 4>(wide);
+        case 8: return u8 ? pick_tl_wide<8, 8>(wide) : pick_tl_wide<8, 4>(wide);
+        case 16: return u8 ? nullptr : pick_tl_wide<16, 4>(wide);
+        default: return nullptr;
+    }
 }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -1001,11 +1088,14 @@ iqa_launch_cfg serve_cfg(int64_t N, int64_t NT) {
     return batch_cfg(N, NT);
 }
 
-// Per (device, stream) workspace for split partials.  Partials are written by
-// tiles_kernel and read by combine_kernel in the same stream order, so one
-// buffer per stream is enough; concurrent streams get their own.  A buffer
-// that is outgrown is kept, not freed: a graph captured earlier may still
-// launch kernels that use it.
+// Per (device, stream) workspace for split tiles: the parts' partial sums and
+// one ticket counter per tile group (see split_finish).  A launch uses its
+// workspace from its first workgroup to its last, and launches on one stream
+// run one after the other, so one buffer per stream is enough; concurrent
+// streams get their own.  A new buffer is cleared on its stream before first
+// use (the counters must start at zero; each launch leaves them at zero).  A
+// buffer that is outgrown is kept, not freed: a graph captured earlier may
+// still launch kernels that use it.
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -1014,31 +1104,33 @@ std::mutex g_ws_mutex;
 std::map<std::pair<int, void *>, Workspace> g_ws;
 std::vector<void *> g_ws_retired;
 
+size_t split_ws_bytes(const Geometry &g, const iqa_launch_cfg &c) {
+    if (c.ksplit <= 1) return 0;
+    return (size_t)split_partials(g.groups, c.ksplit, g.ht) * 4 * sizeof(float) +
+           (size_t)g.groups * sizeof(uint32_t);
+}
+
 iqa_status workspace_for(hipStream_t s, size_t bytes, float **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) {
-        g_last_hip_error = (int)e;
-        return IQA_ERR_HIP;
-    }
+    if (e != hipSuccess) return hip_status(e);
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     Workspace &w = g_ws[{dev, (void *)s}];
     if (w.bytes < bytes) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (s != nullptr) {
             e = hipStreamIsCapturing(s, &cs);
-            if (e != hipSuccess) {
-                g_last_hip_error = (int)e;
-                return IQA_ERR_HIP;
-            }
+            if (e != hipSuccess) return hip_status(e);
         }
         if (cs != hipStreamCaptureStatusNone) return IQA_ERR_CAPTURE;
         const size_t nb = (std::max(bytes, w.bytes) + 4095) & ~size_t(4095);
         void *p = nullptr;
         e = hipMalloc(&p, nb);
+        if (e != hipSuccess) return hip_status(e);
+        e = hipMemsetAsync(p, 0, nb, s);
         if (e != hipSuccess) {
-            g_last_hip_error = (int)e;
-            return IQA_ERR_HIP;
+            (void)hipFree(p);
+            return hip_status(e);
         }
         if (w.ptr) g_ws_retired.push_back(w.ptr);
         w.ptr = p;
@@ -1075,35 +1167,39 @@ void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, 
     a.sums = sums;
 }
 
+// Where a launch's split workspace comes from.
+enum class Ws {
+    kLibrary,   // the per-(device, stream) buffer, grown on demand
+    kPrepare,   // only allocate the library buffer, launch nothing
+};
+
 iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
                float C2, float C, float *lisi, float *aug, float *sums,
-               const iqa_launch_cfg *cfg_in, void *stream, bool prepare_only) {
+               const iqa_launch_cfg *cfg_in, void *stream, Ws ws, uint64_t *tl = nullptr) {
     iqa_launch_cfg c = cfg_in ? *cfg_in : pick_cfg(N, NT, x, y);
     Geometry g{};
     iqa_status st = geometry(N, NT, c, g);
     if (st != IQA_OK) return st;
-    if (!prepare_only) {
+    if (ws != Ws::kPrepare) {
         if (!aligned(x, 4 * c.vec) || !aligned(y, 4 * c.vec)) return IQA_ERR_ALIGN;
     }
     int mode = ((lisi || sums) ? kLisi : 0) | ((aug || sums) ? kAug : 0);
     if (mode == 0) mode = kBoth;
     const bool wide = g.cpl > 1;
-    LaunchFn fn = pick(c, mode, wide);
+    LaunchFn fn = tl ? pick_tl(c, wide) : pick(c, mode, wide);
     if (!fn) return IQA_ERR_CONFIG;
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     KArgs a{};
-    if (c.ksplit > 1) {
-        const size_t bytes = (size_t)g.groups * c.ksplit * g.ht * 4 * sizeof(float);
+    const size_t bytes = split_ws_bytes(g, c);
+    if (bytes > 0) {
         st = workspace_for(s, bytes, &a.ws);
         if (st != IQA_OK) return st;
     }
-    if (prepare_only) return IQA_OK;
+    if (ws == Ws::kPrepare) return IQA_OK;
 
     fill_args(a, x, y, N, NT, D, C1, C2, C, lisi, aug, sums, c, g);
-    hipError_t e = fn(a, (unsigned)g.grid, s);
-    if (e == hipSuccess && c.ksplit > 1) e = launch_combine(a, mode, s);
-    return hip_status(e);
+    return hip_status(fn(a, tl, (unsigned)g.grid, s));
 }
 
 iqa_status check_common(const float *x, const float *y, int64_t N, int64_t NT) {
@@ -1149,12 +1245,37 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT, 
     if (st != IQA_OK) return st;
     st = check_outputs_params(lisi, auglisi, sums, D, C1, C2, C);
     if (st != IQA_OK) return st;
-    return run(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, cfg, stream, false);
+    return run(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, cfg, stream, Ws::kLibrary);
 }
 
 iqa_status iqa_tiles(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
                      float C2, float C, float *lisi, float *auglisi, float *sums, void *stream) {
     return iqa_tiles_cfg(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, nullptr, stream);
+}
+
+iqa_status iqa_tiles_timeline(const float *x, const float *y, int64_t N, int64_t NT, float D,
+                              float C1, float C2, float C, float *lisi, float *auglisi,
+                              float *sums, const iqa_launch_cfg *cfg, uint64_t *stamps,
+                              int64_t stamp_count, void *stream) {
+    iqa_status st = check_common(x, y, N, NT);
+    if (st != IQA_OK) return st;
+    st = check_outputs_params(lisi, auglisi, sums, D, C1, C2, C);
+    if (st != IQA_OK) return st;
+    if (!stamps) return IQA_ERR_NULL;
+    if (!aligned(stamps, 8)) return IQA_ERR_ALIGN;
+    const iqa_launch_cfg c = cfg ? *cfg : pick_cfg(N, NT, x, y);
+    Geometry g{};
+    st = geometry(N, NT, c, g);
+    if (st != IQA_OK) return st;
+    if (stamp_count < 8 * g.grid) return IQA_ERR_SHAPE;
+    return run(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, &c, stream, Ws::kLibrary, stamps);
+}
+
+int64_t iqa_launch_workgroups(int64_t N, int64_t NT, const iqa_launch_cfg *cfg) {
+    if (!cfg || check_shape(N, NT) != IQA_OK) return -1;
+    Geometry g{};
+    if (geometry(N, NT, *cfg, g) != IQA_OK) return -1;
+    return g.grid;
 }
 
 iqa_status lisi_tiles(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
@@ -1164,7 +1285,8 @@ iqa_status lisi_tiles(const float *x, const float *y, int64_t N, int64_t NT, flo
     if (!lisi) return IQA_ERR_NULL;
     if (!aligned(lisi, 4)) return IQA_ERR_ALIGN;
     if (!param_ok(D) || !param_ok(C1) || !param_ok(C2)) return IQA_ERR_PARAM;
-    return run(x, y, N, NT, D, C1, C2, 1.0f, lisi, nullptr, nullptr, nullptr, stream, false);
+    return run(x, y, N, NT, D, C1, C2, 1.0f, lisi, nullptr, nullptr, nullptr, stream,
+               Ws::kLibrary);
 }
 
 iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT, float C,
@@ -1175,7 +1297,7 @@ iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT, 
     if (!aligned(auglisi, 4)) return IQA_ERR_ALIGN;
     if (!param_ok(C)) return IQA_ERR_PARAM;
     return run(x, y, N, NT, 1.0f, 1.0f, 1.0f, C, nullptr, auglisi, nullptr, nullptr, stream,
-               false);
+               Ws::kLibrary);
 }
 
 iqa_status iqa_default_cfg(int64_t N, int64_t NT, const float *x, const float *y,
@@ -1200,7 +1322,7 @@ iqa_status iqa_prepare(int64_t N, int64_t NT, const iqa_launch_cfg *cfg, void *s
     if (st != IQA_OK) return st;
     const float *probe = reinterpret_cast<const float *>(uintptr_t(256));
     return run(probe, probe, N, NT, 1.f, 1.f, 1.f, 1.f, nullptr, nullptr, nullptr, cfg, stream,
-               true);
+               Ws::kPrepare);
 }
 
 iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *cfg) {
@@ -1374,6 +1496,6 @@ const char *iqa_status_str(int status) {
 
 int iqa_last_hip_error(void) { return g_last_hip_error; }
 
-int iqa_version(void) { return 300; }
+int iqa_version(void) { return 400; }
 
 }  // extern "C"

@@ -163,6 +163,19 @@ bool iqa_server::launch(Slot &s, std::vector<Pending> &batch) {
     std::vector<iqa_pair> pairs(batch.size());
     int64_t arena_off = 0;
     bool ok = true;
+    // The batch's stream waits for every request's ready event (each distinct
+    // event once) before anything reads a snapshot or writes an output.
+    void *waited = nullptr;
+    for (size_t i = 0; i < batch.size() && ok; ++i) {
+        void *ev = batch[i].req.ready_event;
+        if (!ev || ev == waited) continue;
+        hipError_t e = hipStreamWaitEvent(s.stream, static_cast<hipEvent_t>(ev), 0);
+        if (e != hipSuccess) {
+            last_hip_error = (int)e;
+            ok = false;
+        }
+        waited = ev;
+    }
     for (size_t i = 0; i < batch.size(); ++i) {
         const iqa_request &r = batch[i].req;
         const Ref &ref = refs[r.ref_id];
@@ -471,7 +484,7 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
             iqa_completion c{};
             c.tag = r.tag;
             c.status = st;
-            c.t_submit_ns = c.t_admit_ns = c.t_launch_ns = c.t_done_ns = t;
+            c.t_submit_ns = c.t_admit_ns = c.t_launch_ns = c.t_done_ns = c.t_poll_ns = t;
             sv->done.push_back(c);
             ++rejected;
             continue;
@@ -495,13 +508,17 @@ iqa_status iqa_server_submit(iqa_server *sv, const iqa_request *reqs, int64_t co
 int64_t iqa_server_poll(iqa_server *sv, iqa_completion *out, int64_t max) {
     if (!sv || !out || max <= 0) return 0;
     if (sv->done_n.load(std::memory_order_acquire) == 0) return 0;
-    std::lock_guard<std::mutex> lock(sv->mu);
     int64_t n = 0;
-    while (n < max && !sv->done.empty()) {
-        out[n++] = sv->done.front();
-        sv->done.pop_front();
+    {
+        std::lock_guard<std::mutex> lock(sv->mu);
+        while (n < max && !sv->done.empty()) {
+            out[n++] = sv->done.front();
+            sv->done.pop_front();
+        }
+        sv->done_n.store((int64_t)sv->done.size(), std::memory_order_relaxed);
     }
-    sv->done_n.store((int64_t)sv->done.size(), std::memory_order_relaxed);
+    const int64_t t = now_ns();
+    for (int64_t i = 0; i < n; ++i) out[i].t_poll_ns = t;
     return n;
 }
 
@@ -572,6 +589,7 @@ iqa_status iqa_server_replay(iqa_server *sv, const iqa_request *reqs,
         out[i].t_admit_ns -= t0;
         out[i].t_launch_ns -= t0;
         out[i].t_done_ns -= t0;
+        out[i].t_poll_ns -= t0;
     }
     return st;
 }

@@ -184,6 +184,61 @@ def read_ceiling(buf: torch.Tensor, out: torch.Tensor, stream=None) -> None:
     _lib.check(st, "iqa_read_ceiling")
 
 
+def launch_workgroups(N: int, NT: int, cfg: dict) -> int:
+    """Workgroups of the single-pair launch for (N, NT) with ``cfg``."""
+    n = int(_lib.load().iqa_launch_workgroups(N, NT, ctypes.byref(LaunchCfg.from_dict(cfg))))
+    if n < 0:
+        raise ValueError(f"invalid shape or configuration: {N} {NT} {cfg}")
+    return n
+
+
+def tiles_timeline(x: torch.Tensor, y: torch.Tensor, NT: int, cfg: dict, stamps: torch.Tensor,
+                   *, C1: float = C_DEFAULT, C2: float = C_DEFAULT, C: float = C_DEFAULT,
+                   D: Optional[float] = None, stream=None,
+                   out: Optional[Dict[str, torch.Tensor]] = None) -> TileResult:
+    """The fused launch with a per-workgroup timeline (diagnostics): ``stamps``
+    is an int64 tensor of at least 8 entries per workgroup (see
+    :func:`launch_workgroups`) that receives wall-clock stamps, hardware ids,
+    tile group and split part of every workgroup."""
+    N = _check_images(x, y)
+    if D is None:
+        D = default_D(C1)
+    if stamps.dtype != torch.int64 or not stamps.is_contiguous() or stamps.device != x.device:
+        raise ValueError("stamps must be a contiguous int64 tensor on the images' device")
+    ns = N // NT if NT > 0 and N % NT == 0 else 0
+    out = out or {}
+    lo = _out((ns, ns), x.device, out.get("lisi"), "lisi")
+    ao = _out((ns, ns), x.device, out.get("auglisi"), "auglisi")
+    with torch.cuda.device(x.device):
+        st = _lib.load().iqa_tiles_timeline(
+            _ptr(x), _ptr(y), N, NT, D, C1, C2, C, _ptr(lo), _ptr(ao), None,
+            ctypes.byref(LaunchCfg.from_dict(cfg)), stamps.data_ptr(), stamps.numel(),
+            _stream_handle(x.device, stream))
+    _lib.check(st, "iqa_tiles_timeline")
+    return TileResult(lo, ao, None)
+
+
+def probe_empty(blocks: int, threads: int, stream=None, device=None) -> None:
+    """One launch of an empty kernel (measurement only)."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(device):
+        st = _lib.load().iqa_probe_empty(blocks, threads, _stream_handle(device, stream))
+    if st != _lib.IQA_OK:
+        raise IqaError(st, "iqa_probe_empty", _lib.load().iqa_probe_last_hip_error())
+
+
+def probe_read(buf: torch.Tensor, out: torch.Tensor, threads: int, loads: int, mode: int,
+               stream=None) -> None:
+    """A plain read of ``buf`` by ``out.numel()`` workgroups (measurement only)."""
+    if buf.dtype != torch.float32 or not buf.is_contiguous() or out.dtype != torch.float32:
+        raise ValueError("probe_read needs contiguous float32 tensors")
+    with torch.cuda.device(buf.device):
+        st = _lib.load().iqa_probe_read(buf.data_ptr(), buf.numel(), out.data_ptr(), out.numel(),
+                                        threads, loads, mode, _stream_handle(buf.device, stream))
+    if st != _lib.IQA_OK:
+        raise IqaError(st, "iqa_probe_read", _lib.load().iqa_probe_last_hip_error())
+
+
 def merge_tiles(sums: torch.Tensor, f: int, *, C1: float = C_DEFAULT, C2: float = C_DEFAULT,
                 C: float = C_DEFAULT, D: Optional[float] = None, stream=None) -> TileResult:
     """Eq. (3)/(4): merge f x f blocks of tiles (given by their (n, 4) sums

@@ -32,20 +32,31 @@ def serve_cfg(N: int, NT: int) -> dict:
 
 
 class ServedRequest:
-    """One request with its own output tensors (kept alive by this object)."""
+    """One request with its own output tensors (kept alive by this object).
+
+    ``ready`` is the event the request's batch waits for on the device before
+    it reads the snapshot or writes the outputs (None: no wait)."""
 
     def __init__(self, snapshot: torch.Tensor, ref_id: int, NT: int, N: int, tag: int,
-                 sums: bool = False, host: bool = False):
+                 sums: bool = False, host: bool = False,
+                 ready: Optional[torch.cuda.Event] = None):
         ns = N // NT if NT > 0 and N % NT == 0 else 0
         dev = torch.device("cuda", torch.cuda.current_device()) if host else snapshot.device
         self.snapshot = snapshot
         self.lisi = torch.empty(ns, ns, device=dev)
         self.auglisi = torch.empty(ns, ns, device=dev)
         self.sums = torch.empty(ns * ns, 4, device=dev) if sums else None
+        if ready is True:
+            # after the outputs' allocation on the current stream (and whatever
+            # that stream still does with their memory, or with the snapshot)
+            ready = torch.cuda.Event()
+            ready.record(torch.cuda.current_stream(dev))
+        self.ready = ready or None
         self.c = Request(None if host else snapshot.data_ptr(),
                          snapshot.data_ptr() if host else None,
                          self.lisi.data_ptr(), self.auglisi.data_ptr(),
-                         self.sums.data_ptr() if sums else None, NT, ref_id, 0, tag)
+                         self.sums.data_ptr() if sums else None, NT, ref_id, 0, tag,
+                         self.ready.cuda_event if self.ready is not None else None)
         self.NT = NT
         self.ref_id = ref_id
         self.tag = tag
@@ -117,16 +128,25 @@ class Server:
         return int(rid.value)
 
     def request(self, snapshot: torch.Tensor, ref_id: int, NT: int, *, sums: bool = False,
-                tag: Optional[int] = None) -> ServedRequest:
+                tag: Optional[int] = None, ready=True) -> ServedRequest:
         """A request for `snapshot` (device tensor, or pinned host tensor) vs
-        reference `ref_id`, with freshly allocated outputs."""
+        reference `ref_id`, with freshly allocated outputs.
+
+        The server's streams are not ordered after the caller's.  ``ready``
+        orders the request's batch after the caller's work: True (default)
+        records an event on the current stream once the outputs are allocated,
+        which covers a snapshot produced on that stream; a ``torch.cuda.Event``
+        recorded by the caller (e.g. on the stream that produced the snapshot)
+        is used as given; False means no wait, for a caller that has
+        synchronised the device (or the producing streams) before submitting."""
         if tag is None:
             tag = self._next_tag
             self._next_tag += 1
         host = snapshot.device.type == "cpu"
         if host and not snapshot.is_pinned():
             raise ValueError("host snapshots must be in pinned memory")
-        return ServedRequest(snapshot, ref_id, NT, self.refs[ref_id].shape[0], tag, sums, host)
+        return ServedRequest(snapshot, ref_id, NT, self.refs[ref_id].shape[0], tag, sums, host,
+                             ready=ready)
 
     def submit(self, reqs: Sequence[ServedRequest]) -> None:
         arr = (Request * len(reqs))(*[r.c for r in reqs])
@@ -193,16 +213,23 @@ class Server:
 def _completion(c: Completion) -> dict:
     return {"tag": int(c.tag), "status": int(c.status), "t_submit_ns": int(c.t_submit_ns),
             "t_admit_ns": int(c.t_admit_ns), "t_launch_ns": int(c.t_launch_ns),
-            "t_done_ns": int(c.t_done_ns)}
+            "t_done_ns": int(c.t_done_ns), "t_poll_ns": int(c.t_poll_ns)}
 
 
 def latency_summary(comps: List[dict]) -> dict:
+    """Latency from submission to the caller's poll returning the completion
+    (p50_us, p99_us, ...), and to the scheduler seeing the batch complete
+    (p50_done_us, p99_done_us); throughput over the span from the first
+    submission to the last poll."""
     ok = [c for c in comps if c["status"] == 0]
-    lat = np.array([c["t_done_ns"] - c["t_submit_ns"] for c in ok], dtype=np.float64) / 1e3
+    lat = np.array([c["t_poll_ns"] - c["t_submit_ns"] for c in ok], dtype=np.float64) / 1e3
+    done = np.array([c["t_done_ns"] - c["t_submit_ns"] for c in ok], dtype=np.float64) / 1e3
     if lat.size == 0:
         return {"completed": 0}
-    span = (max(c["t_done_ns"] for c in ok) - min(c["t_submit_ns"] for c in ok)) / 1e9
+    span = (max(c["t_poll_ns"] for c in ok) - min(c["t_submit_ns"] for c in ok)) / 1e9
     return {"completed": len(ok), "failed": len(comps) - len(ok),
             "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
             "max_us": float(lat.max()), "mean_us": float(lat.mean()),
+            "p50_done_us": float(np.percentile(done, 50)),
+            "p99_done_us": float(np.percentile(done, 99)),
             "throughput_rps": len(ok) / span if span > 0 else float("nan"), "span_s": span}

@@ -8,10 +8,10 @@ configuration the benchmark times.
   against the FP64 oracle, and every pair is bitwise equal to its single-pair
   launch with the batch geometry.
 * Serving: 16 resident references with N round-robin over {1024, 2048, 4096},
-  one snapshot each, N_T from {32, 64}, Poisson arrivals at 20k requests/s.
-  Every result is bitwise equal to the single-pair launch with the batch
-  geometry, and one request per (reference, N_T) is checked against the oracle
-  on every tile.
+  three distinct snapshots each, N_T from {32, 64}, Poisson arrivals at 20k
+  requests/s.  Every result is bitwise equal to the single-pair launch of its
+  own snapshot with the server's geometry, and one request per (reference,
+  N_T) is checked against the oracle on every tile.
 """
 
 from __future__ import annotations
@@ -66,19 +66,22 @@ def test_ragged_batch_full_config():
 
 
 def test_serving_full_config():
+    """400 requests over 16 references with three distinct snapshots each: a
+    request that read another request's snapshot (or reference) would differ
+    from its own single-pair launch."""
     specs = synth.serving_references(count=16, seed=11)
-    print(f"serving: {len(specs)} references", flush=True)
+    print(f"serving: {len(specs)} references x 3 snapshots", flush=True)
     refs, snaps = [], []
     for sp in specs:
         x, _, _ = synth.make_pair(sp)
         refs.append((x, to_dev(x)))
-        s = synth.make_snapshot(sp, 0)
-        snaps.append((s, to_dev(s)))
+        snaps.append([(s, to_dev(s)) for s in (synth.make_snapshot(sp, k) for k in range(3))])
     rng = np.random.default_rng(21)
-    plan = [(int(rng.integers(len(specs))), int(rng.choice([32, 64]))) for _ in range(400)]
+    plan = [(int(rng.integers(len(specs))), int(rng.integers(3)), int(rng.choice([32, 64])))
+            for _ in range(400)]
     with Server(16 << 30, streams=2, max_batch=512) as srv:
         ids = [srv.add_reference(d) for _, d in refs]
-        reqs = [srv.request(snaps[r][1], ids[r], NT) for r, NT in plan]
+        reqs = [srv.request(snaps[r][k][1], ids[r], NT) for r, k, NT in plan]
         arrivals = synth.poisson_arrivals(20000.0, len(reqs), seed=4)
         comps = srv.replay(reqs, arrivals, timeout_s=120.0)
         st = srv.stats()
@@ -86,15 +89,27 @@ def test_serving_full_config():
     assert st["completed"] == len(reqs) and st["rejected"] == 0
 
     singles = {}
-    for (r, NT), req in zip(plan, reqs):
-        if (r, NT) not in singles:
+    for (r, k, NT), req in zip(plan, reqs):
+        if (r, k, NT) not in singles:
             N = specs[r].N
-            singles[(r, NT)] = iqa_tiles(snaps[r][1], refs[r][1], NT, cfg=serve_cfg(N, NT))
+            singles[(r, k, NT)] = iqa_tiles(snaps[r][k][1], refs[r][1], NT, cfg=serve_cfg(N, NT))
             torch.cuda.synchronize()
-        one = singles[(r, NT)]
-        assert same(one.lisi, req.lisi) and same(one.auglisi, req.auglisi), (r, NT)
-    for (r, NT), one in singles.items():
-        assert_parity(one, oracle_for(snaps[r][0], refs[r][0], NT), what=f"ref {r} NT={NT}")
+        one = singles[(r, k, NT)]
+        assert same(one.lisi, req.lisi) and same(one.auglisi, req.auglisi), (r, k, NT)
+    # the snapshots of one reference differ, so their results do too
+    for r in range(len(specs)):
+        got = [singles.get((r, k, 64)) for k in range(3)]
+        got = [g for g in got if g is not None]
+        for a, b in zip(got, got[1:]):
+            assert not same(a.auglisi, b.auglisi), r
+    # every (reference, N_T) against the oracle on one of its snapshots
+    seen = set()
+    for (r, k, NT), one in singles.items():
+        if (r, NT) in seen:
+            continue
+        seen.add((r, NT))
+        assert_parity(one, oracle_for(snaps[r][k][0], refs[r][0], NT),
+                      what=f"ref {r} snapshot {k} NT={NT}")
 
 
 def test_serving_under_overload():

@@ -177,3 +177,55 @@ def test_server_holds_dropped_requests_until_completion_is_seen(world):
         gc.collect()
         assert w() is None
         assert len(srv.poll()) == 1
+
+
+def test_ready_event_orders_batch_after_producer_stream(world):
+    """A snapshot written by a torch op on a side stream right before submit
+    (behind a long fill on that stream) is read only after the write: the
+    request carries an event recorded on the side stream, and its result
+    equals the single-pair launch on the finished snapshot, bitwise."""
+    specs, refs, snaps = world
+    r = 3
+    N = refs[r][1].shape[0]
+    side = torch.cuda.Stream()
+    busy = torch.empty(256 << 20, device="cuda")       # 1 GiB: a fill of ~0.2 ms
+    srv, ids = make_server(refs)
+    reqs, dsts = [], []
+    for k in range(8):
+        dst = torch.zeros(N, N, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            busy.fill_(float(k))
+            dst.copy_(snaps[r][k % 2][1])
+            dst.record_stream(side)
+            ev = torch.cuda.Event()
+            ev.record(side)
+        req = srv.request(dst, ids[r], 64, ready=ev)
+        srv.submit([req])
+        reqs.append((req, k % 2))
+        dsts.append(dst)
+    srv.drain()
+    comps = srv.poll(100)
+    srv.close()
+    assert len(comps) == 8 and all(c["status"] == 0 for c in comps)
+    torch.cuda.synchronize()
+    single = [iqa_tiles(snaps[r][k][1], refs[r][1], 64, cfg=serve_cfg(N, 64)) for k in range(2)]
+    torch.cuda.synchronize()
+    for req, k in reqs:
+        assert same(single[k].lisi, req.lisi) and same(single[k].auglisi, req.auglisi)
+
+
+def test_completion_times_are_ordered_to_the_poll(world):
+    specs, refs, snaps = world
+    srv, ids = make_server(refs)
+    reqs = [srv.request(snaps[r % 4][0][1], ids[r % 4], 32) for r in range(32)]
+    srv.submit(reqs)
+    srv.drain()
+    comps = srv.poll(100)
+    srv.close()
+    assert len(comps) == 32
+    for c in comps:
+        assert c["t_submit_ns"] <= c["t_admit_ns"] <= c["t_launch_ns"] <= c["t_done_ns"]
+        assert c["t_done_ns"] <= c["t_poll_ns"]
+    summ = latency_summary(comps)
+    assert summ["p50_done_us"] <= summ["p50_us"]
