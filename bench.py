@@ -52,6 +52,11 @@ PROFILES = os.path.join(ROOT, "profiles")
 SWEEP_CELLS = [(N, NT) for N in (1024, 2048, 4096, 8192) for NT in (16, 32, 64, 128, 256)]
 
 
+def log(msg: str) -> None:
+    """Progress of the run, on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +258,7 @@ def run_serving(torch, world, rate: float, seconds: float, budget: int = 16 << 3
         streams = 2 if host else 4
     from paper_2501_10653_amd.serve import Server, latency_summary
     count = max(200, int(rate * seconds))
+    log(f"serving {rate:.0f} req/s ({'host' if host else 'device'} snapshots)")
     arena = (2 << 30) if host else 0
     if host:
         world.pin_snapshots()
@@ -615,6 +621,7 @@ def main(argv=None) -> int:
     bytes_step = bytes_pair + 2 * 4 * ns * ns
     gbs = bytes_step / (ms_step * 1e-3) / 1e9
 
+    log(f"headline: {ms_step * 1e3:.3f} us per launch over {K} launches")
     gpu_lisi = lisi.cpu().numpy()
     gpu_aug = aug.cpu().numpy()
     if use_graph:
@@ -622,10 +629,13 @@ def main(argv=None) -> int:
 
     extras, batched, floor = {}, None, None
     if not args.no_extras:
+        log("read floor (quick)")
         floor = quick_read_floor(torch, dev, bytes_pair, args.pool_bytes)
+        log("read ceiling, separate kernels")
         extras = run_extras(torch, dev, xs, ys, N, NT, pool, stream, read_ceiling,
                             lisi_tiles, auglisi_tiles, iqa_tiles, cfg, bytes_pair)
         extras["kernel_frac_of_read_ceiling"] = round(gbs / extras["read_ceiling_gbs"], 4)
+        log("same-shape batch")
         batched = run_same_shape_batch(torch, xs, ys, NT, stream, bytes_pair, ms_step)
         batched["frac_of_read_ceiling"] = round(batched["gbs"] / extras["read_ceiling_gbs"], 4)
 
@@ -674,14 +684,17 @@ def main(argv=None) -> int:
     del xs, ys
     torch.cuda.empty_cache()
     if not args.no_extras and args.workload == "paper":
+        log("ragged batch")
         line["ragged"] = run_ragged(torch, dev)
     if args.serve_rates and not args.no_extras and args.workload == "paper":
+        log("serving")
         world = ServingWorld(torch, dev)
         line["serving"] = [run_serving(torch, world, float(r), args.serve_seconds, seed=i)
                            for i, r in enumerate(args.serve_rates.split(","))]
         del world
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(x, y, NT, args.cpu_runs, gpu_lisi, gpu_aug)
         line["cpu_baseline"]["cpu_model"] = cpu_model()
     else:

@@ -512,44 +512,86 @@ __device__ __forceinline__ float4 wave_tree(float4 (&v)[WAVES]) {
 //
 // With ks > 1 workgroups per tile group, every part stores its partial sums
 // (one float4 per tile) and then takes a ticket from the group's counter.
-// The part that draws the last ticket has seen, through the counter's
-// release/acquire chain at agent scope, every other part's partials: it adds
-// them in part order (Kahan-compensated, the same order whichever part comes
-// last, so results are bitwise reproducible), finalises, and sets the counter
-// back to zero for the next launch.  No part waits for another.
+// The part that draws the last ticket has seen every other part's partials:
+// it adds them and finalises, and sets the counter back to zero for the next
+// launch.  No part waits for another.
 //
-// Workspace layout: partials [group][part][ht] float4, then one 32-bit
-// counter per group.  Counters start at zero and every launch leaves them at
-// zero.
+// The parts run on different XCDs, whose L2 caches are not coherent with one
+// another, so the partials travel by device-coherent accesses (agent-scope
+// atomic stores and loads, which bypass the non-coherent cache levels), and
+// only the ordering is left to the counter: a part's partial stores have
+// completed (vmcnt 0) before it takes its ticket, and the last part issues
+// its partial loads only after its ticket has returned.
+//
+// The last part adds the partials the way the kernel adds pixels: lane q of
+// tile j's lane group Kahan-adds parts q, q + g, q + 2g, ... (g lanes per
+// tile), then the group is summed with the same fixed DPP tree.  The order
+// does not depend on which part came last, so results are bitwise
+// reproducible.
+//
+// Workspace: partials [group][part][ht] float4 from a.ws on, and one 32-bit
+// counter per group just below a.ws (group g's at a.ws - 4 (g + 1) bytes), in
+// a counter region that holds nothing but counters.  The counters start at
+// zero and every launch leaves the ones it used at zero, so a region reused by
+// shapes of any size is all zeros between launches.
 __host__ __device__ __forceinline__ int64_t split_partials(int64_t groups, int64_t ks, int64_t ht) {
     return groups * ks * ht;   // float4 entries
 }
 
+__device__ __forceinline__ void store_coherent(float4 *p, float4 v) {
+    uint64_t *q = reinterpret_cast<uint64_t *>(p);
+    const uint64_t lo = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+    const uint64_t hi = (uint64_t)__float_as_uint(v.z) | ((uint64_t)__float_as_uint(v.w) << 32);
+    __hip_atomic_store(q, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float4 load_coherent(const float4 *p) {
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+    const uint64_t lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return float4{__uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)(lo >> 32)),
+                  __uint_as_float((uint32_t)hi), __uint_as_float((uint32_t)(hi >> 32))};
+}
+
+// Wait until this wave's vector memory operations have completed.
+__device__ __forceinline__ void wait_vmem() {
+    __builtin_amdgcn_s_waitcnt(/*vmcnt*/ 0 | (/*expcnt*/ 0x7 << 4) | (/*lgkmcnt*/ 0xf << 8));
+}
+
 template <int MODE>
-__device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, int lane,
-                                             bool mine, int jt, int64_t t, float4 v) {
+__device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, int lane, bool mine,
+                                             int jt, int ty, int txg, float4 v) {
     float4 *ws = reinterpret_cast<float4 *>(a.ws);
     const int64_t base = (int64_t)grp * a.ks;
-    if (mine) ws[(base + part) * a.ht + jt] = v;
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(
-                        ws + split_partials((int64_t)a.ns * a.ngx, a.ks, a.ht)) + grp;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (mine) store_coherent(ws + (base + part) * a.ht + jt, v);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(a.ws) - 1 - grp;
+    wait_vmem();                                        // partials stored before the ticket
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     uint32_t ticket = 0;
     if (lane == 0) ticket = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);    // waits for the returned value
     if (ticket != (uint32_t)(a.ks - 1)) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (mine) {
-        Acc c = acc_zero();
-        for (int p = 0; p < a.ks; ++p) {
-            const float4 w = ws[(base + p) * a.ht + jt];
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+    // Lane group of tile j: 2^log_grp lanes, lane q of the group takes parts
+    // q, q + g, ...
+    const int g = 1 << a.log_grp;
+    const int j = lane >> a.log_grp;
+    const int q = lane & (g - 1);
+    const int tx = txg * a.ht + j;
+    Acc c = acc_zero();
+    if (tx < a.ns) {
+        for (int p = q; p < a.ks; p += g) {
+            const float4 w = load_coherent(ws + (base + p) * a.ht + j);
             if constexpr ((MODE & kLisi) != 0) cadd(c.A, w.x);
             if constexpr ((MODE & kAug) != 0) cadd(c.P, w.y);
             cadd(c.X, w.z);
             cadd(c.Y, w.w);
         }
-        finalize<MODE>(a, t, c);
     }
+    const Sum4 s = group_allreduce<MODE>(fold(c), a.log_grp);
+    if (q == 0 && tx < a.ns) finalize<MODE>(a, (int64_t)ty * a.ns + tx, acc_of(s));
     if (lane == 0) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -561,13 +603,16 @@ __device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, 
 // rows are cut into WAVES*ks contiguous slices of rows_wave rows; wave w of
 // part p takes slice p*WAVES + w.
 //
+// SPLIT kernels (ks > 1 workgroups per tile group) finish through
+// split_finish; the others finalise directly, and carry no split code.
+//
 // TL (diagnostic launches only) records, per workgroup, wall-clock stamps of
 // wave 0: entry, its first batch of rows reduced (first loads back), its last
 // rows reduced (last loads back), and its exit after the results are stored,
 // plus the XCD and hardware slot it ran on: 8 uint64 per workgroup at
 // tl[8 * blockIdx.x], written with ordinary vector stores.
-template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool TL>
-__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a, uint64_t *tl) {
+template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool SPLIT, bool TL>
+__device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
     uint64_t ts[4] = {0, 0, 0, 0};
     if constexpr (TL) ts[0] = wall_clock64();
     const int lane = threadIdx.x & (kWave - 1);
@@ -603,11 +648,11 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a, uint64_t 
             v = wave_tree<WAVES>(w);
         }
     }
-    const int64_t t = (int64_t)ty * a.ns + txg * a.ht + jt;
-    if (a.ks == 1) {
-        if (mine) finalize<MODE>(a, t, acc_of(Sum4{v.x, v.y, v.z, v.w}));
+    if constexpr (!SPLIT) {
+        if (mine) finalize<MODE>(a, (int64_t)ty * a.ns + txg * a.ht + jt,
+                                 acc_of(Sum4{v.x, v.y, v.z, v.w}));
     } else {
-        split_finish<MODE>(a, grp, part, lane, mine, jt, t, v);
+        split_finish<MODE>(a, grp, part, lane, mine, jt, ty, txg, v);
     }
     if constexpr (TL) {
         if (wave == 0) {
@@ -626,6 +671,16 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a, uint64_t 
             }
         }
     }
+}
+
+template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool SPLIT>
+__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
+    tiles_body<VEC, WAVES, U, MODE, WIDE, SPLIT, false>(a, nullptr);
+}
+
+template <int VEC, int WAVES, int U, bool WIDE, bool SPLIT>
+__global__ __launch_bounds__(WAVES * kWave) void tiles_kernel_tl(KArgs a, uint64_t *tl) {
+    tiles_body<VEC, WAVES, U, kBoth, WIDE, SPLIT, true>(a, tl);
 }
 
 // ---------------------------------------------------------------------------
@@ -856,75 +911,75 @@ iqa_status hip_status(hipError_t e) {
 
 using LaunchFn = hipError_t (*)(const KArgs &, uint64_t *, unsigned, hipStream_t);
 
-template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool TL>
-hipError_t launch_impl(const KArgs &a, uint64_t *tl, unsigned grid, hipStream_t s) {
-    return launch_kernel(&tiles_kernel<VEC, WAVES, U, MODE, WIDE, TL>, grid, WAVES * kWave, s, a,
+template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool SPLIT>
+hipError_t launch_impl(const KArgs &a, uint64_t *, unsigned grid, hipStream_t s) {
+    return launch_kernel(&tiles_kernel<VEC, WAVES, U, MODE, WIDE, SPLIT>, grid, WAVES * kWave, s,
+                         a);
+}
+
+template <int VEC, int WAVES, int U, bool WIDE, bool SPLIT>
+hipError_t launch_tl(const KArgs &a, uint64_t *tl, unsigned grid, hipStream_t s) {
+    return launch_kernel(&tiles_kernel_tl<VEC, WAVES, U, WIDE, SPLIT>, grid, WAVES * kWave, s, a,
                          tl);
 }
 
-template <int VEC, int WAVES, int U, bool WIDE>
-LaunchFn pick_mode(int mode) {
-    switch (mode) {
-        case kLisi: return &launch_impl<VEC, WAVES, U, kLisi, WIDE, false>;
-        case kAug: return &launch_impl<VEC, WAVES, U, kAug, WIDE, false>;
-        default: return &launch_impl<VEC, WAVES, U, kBoth, WIDE, false>;
+// What a launch needs, mapped onto the instantiated kernels.
+struct Want {
+    int mode;
+    bool wide, split, tl;
+};
+
+template <int VEC, int WAVES, int U, bool WIDE, bool SPLIT>
+LaunchFn pick_mode(const Want &w) {
+    if (w.tl) {
+        if constexpr (VEC == 4) return &launch_tl<VEC, WAVES, U, WIDE, SPLIT>;
+        return nullptr;
+    }
+    switch (w.mode) {
+        case kLisi: return &launch_impl<VEC, WAVES, U, kLisi, WIDE, SPLIT>;
+        case kAug: return &launch_impl<VEC, WAVES, U, kAug, WIDE, SPLIT>;
+        default: return &launch_impl<VEC, WAVES, U, kBoth, WIDE, SPLIT>;
     }
 }
 
 template <int VEC, int WAVES, int U>
-LaunchFn pick_wide(int mode, bool wide) {
-    return wide ? pick_mode<VEC, WAVES, U, true>(mode) : pick_mode<VEC, WAVES, U, false>(mode);
+LaunchFn pick_shape(const Want &w) {
+    if (w.wide) {
+        return w.split ? pick_mode<VEC, WAVES, U, true, true>(w)
+                       : pick_mode<VEC, WAVES, U, true, false>(w);
+    }
+    return w.split ? pick_mode<VEC, WAVES, U, false, true>(w)
+                   : pick_mode<VEC, WAVES, U, false, false>(w);
 }
 
 template <int VEC, int WAVES>
-LaunchFn pick_unroll(int unroll, int mode, bool wide) {
+LaunchFn pick_unroll(int unroll, const Want &w) {
     switch (unroll) {
-        case 4: return pick_wide<VEC, WAVES, 4>(mode, wide);
-        case 8: return pick_wide<VEC, WAVES, 8>(mode, wide);
+        case 4: return pick_shape<VEC, WAVES, 4>(w);
+        case 8: return pick_shape<VEC, WAVES, 8>(w);
         default: return nullptr;
     }
 }
 
 // The instantiated launch shapes: waves 1/2/4/8 with unroll 4/8 and waves 16
 // with unroll 4 for vec 4, and waves 1/4 with unroll 4 for the narrow vec 2
-// and vec 1 paths.
-LaunchFn pick(const iqa_launch_cfg &c, int mode, bool wide) {
+// and vec 1 paths; each with and without a row split across workgroups.
+// Timeline launches exist for the vec 4 shapes, fused mode.
+LaunchFn pick(const iqa_launch_cfg &c, const Want &w) {
     if (c.vec == 4) {
         switch (c.waves) {
-            case 1: return pick_unroll<4, 1>(c.unroll, mode, wide);
-            case 2: return pick_unroll<4, 2>(c.unroll, mode, wide);
-            case 4: return pick_unroll<4, 4>(c.unroll, mode, wide);
-            case 8: return pick_unroll<4, 8>(c.unroll, mode, wide);
-            case 16: return c.unroll == 4 ? pick_wide<4, 16, 4>(mode, wide) : nullptr;
+            case 1: return pick_unroll<4, 1>(c.unroll, w);
+            case 2: return pick_unroll<4, 2>(c.unroll, w);
+            case 4: return pick_unroll<4, 4>(c.unroll, w);
+            case 8: return pick_unroll<4, 8>(c.unroll, w);
+            case 16: return c.unroll == 4 ? pick_shape<4, 16, 4>(w) : nullptr;
             default: return nullptr;
         }
     }
-    if (c.unroll != 4 || !(c.waves == 1 || c.waves == 4)) return nullptr;
-    if (c.vec == 2) return c.waves == 1 ? pick_wide<2, 1, 4>(mode, wide) : pick_wide<2, 4, 4>(mode, wide);
-    if (c.vec == 1) return c.waves == 1 ? pick_wide<1, 1, 4>(mode, wide) : pick_wide<1, 4, 4>(mode, wide);
+    if (w.tl || c.unroll != 4 || !(c.waves == 1 || c.waves == 4)) return nullptr;
+    if (c.vec == 2) return c.waves == 1 ? pick_shape<2, 1, 4>(w) : pick_shape<2, 4, 4>(w);
+    if (c.vec == 1) return c.waves == 1 ? pick_shape<1, 1, 4>(w) : pick_shape<1, 4, 4>(w);
     return nullptr;
-}
-
-// Timeline launches (diagnostics): the fused kernel with stamps, for the vec 4
-// shapes.
-template <int WAVES, int U>
-LaunchFn pick_tl_wide(bool wide) {
-    return wide ? &launch_impl<4, WAVES, U, kBoth, true, true>
-                : &launch_impl<4, WAVES, U, kBoth, false, true>;
-}
-
-LaunchFn pick_tl(const iqa_launch_cfg &c, bool wide) {
-    if (c.vec != 4) return nullptr;
-    const bool u8 = c.unroll == 8;
-    if (c.unroll != 4 && c.unroll != 8) return nullptr;
-    switch (c.waves) {
-        case 1: return u8 ? pick_tl_wide<1, 8>(wide) : pick_tl_wide<1, 4>(wide);
-        case 2: return u8 ? pick_tl_wide<2, 8>(wide) : pick_tl_wide<2, 4>(wide);
-        case 4: return u8 ? pick_tl_wide<4, 8>(wide) : pick_tl_wide<4, 4>(wide);
-        case 8: return u8 ? pick_tl_wide<8, 8>(wide) : pick_tl_wide<8, 4>(wide);
-        case 16: return u8 ? nullptr : pick_tl_wide<16, 4>(wide);
-        default: return nullptr;
-    }
 }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -962,7 +1017,7 @@ iqa_status geometry(int64_t N, int64_t NT, const iqa_launch_cfg &c, Geometry &g)
     if (!is_pow2(c.seg) || !is_pow2(c.rp) || (int64_t)c.seg * c.rp > kWave) return IQA_ERR_CONFIG;
     if (!is_pow2(c.waves) || c.waves > 16) return IQA_ERR_CONFIG;
     if (c.ksplit < 1 || NT % ((int64_t)c.waves * c.ksplit) != 0) return IQA_ERR_CONFIG;
-    if (pick(c, kBoth, false) == nullptr) return IQA_ERR_CONFIG;
+    if (pick(c, Want{kBoth, false, false, false}) == nullptr) return IQA_ERR_CONFIG;
     g.ns = N / NT;
     g.ht = kWave / ((int64_t)c.seg * c.rp);
     g.ngx = (g.ns + g.ht - 1) / g.ht;
@@ -1088,55 +1143,69 @@ iqa_launch_cfg serve_cfg(int64_t N, int64_t NT) {
     return batch_cfg(N, NT);
 }
 
-// Per (device, stream) workspace for split tiles: the parts' partial sums and
-// one ticket counter per tile group (see split_finish).  A launch uses its
+// Per (device, stream) workspace for split tiles: a counter region (ticket
+// counters only) followed by a partial-sum region.  A launch uses its
 // workspace from its first workgroup to its last, and launches on one stream
 // run one after the other, so one buffer per stream is enough; concurrent
 // streams get their own.  A new buffer is cleared on its stream before first
-// use (the counters must start at zero; each launch leaves them at zero).  A
-// buffer that is outgrown is kept, not freed: a graph captured earlier may
-// still launch kernels that use it.
+// use, and since each launch leaves its counters at zero, the counter region
+// stays all zeros between launches whatever shapes share it.  A buffer that
+// is outgrown is kept, not freed: a graph captured earlier may still launch
+// kernels that use it.
 struct Workspace {
     void *ptr = nullptr;
-    size_t bytes = 0;
+    size_t cnt_bytes = 0;    // counter region, at ptr
+    size_t part_bytes = 0;   // partial-sum region, at ptr + cnt_bytes
 };
 std::mutex g_ws_mutex;
 std::map<std::pair<int, void *>, Workspace> g_ws;
 std::vector<void *> g_ws_retired;
 
-size_t split_ws_bytes(const Geometry &g, const iqa_launch_cfg &c) {
-    if (c.ksplit <= 1) return 0;
-    return (size_t)split_partials(g.groups, c.ksplit, g.ht) * 4 * sizeof(float) +
-           (size_t)g.groups * sizeof(uint32_t);
+struct SplitNeed {
+    size_t cnt_bytes = 0, part_bytes = 0;   // 0, 0: the launch does not split
+};
+
+SplitNeed split_need(const Geometry &g, const iqa_launch_cfg &c) {
+    SplitNeed n;
+    if (c.ksplit <= 1) return n;
+    n.cnt_bytes = (size_t)g.groups * sizeof(uint32_t);
+    n.part_bytes = (size_t)split_partials(g.groups, c.ksplit, g.ht) * 4 * sizeof(float);
+    return n;
 }
 
-iqa_status workspace_for(hipStream_t s, size_t bytes, float **out) {
+size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+// *part receives the partial-sum region; the counter region ends where it
+// starts.
+iqa_status workspace_for(hipStream_t s, const SplitNeed &need, float **part) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_status(e);
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     Workspace &w = g_ws[{dev, (void *)s}];
-    if (w.bytes < bytes) {
+    if (w.cnt_bytes < need.cnt_bytes || w.part_bytes < need.part_bytes) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (s != nullptr) {
             e = hipStreamIsCapturing(s, &cs);
             if (e != hipSuccess) return hip_status(e);
         }
         if (cs != hipStreamCaptureStatusNone) return IQA_ERR_CAPTURE;
-        const size_t nb = (std::max(bytes, w.bytes) + 4095) & ~size_t(4095);
+        const size_t cb = round_up(std::max(need.cnt_bytes, w.cnt_bytes), 4096);
+        const size_t pb = round_up(std::max(need.part_bytes, w.part_bytes), 4096);
         void *p = nullptr;
-        e = hipMalloc(&p, nb);
+        e = hipMalloc(&p, cb + pb);
         if (e != hipSuccess) return hip_status(e);
-        e = hipMemsetAsync(p, 0, nb, s);
+        e = hipMemsetAsync(p, 0, cb + pb, s);
         if (e != hipSuccess) {
             (void)hipFree(p);
             return hip_status(e);
         }
         if (w.ptr) g_ws_retired.push_back(w.ptr);
         w.ptr = p;
-        w.bytes = nb;
+        w.cnt_bytes = cb;
+        w.part_bytes = pb;
     }
-    *out = static_cast<float *>(w.ptr);
+    *part = reinterpret_cast<float *>(static_cast<char *>(w.ptr) + w.cnt_bytes);
     return IQA_OK;
 }
 
@@ -1185,15 +1254,14 @@ iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, f
     }
     int mode = ((lisi || sums) ? kLisi : 0) | ((aug || sums) ? kAug : 0);
     if (mode == 0) mode = kBoth;
-    const bool wide = g.cpl > 1;
-    LaunchFn fn = tl ? pick_tl(c, wide) : pick(c, mode, wide);
+    LaunchFn fn = pick(c, Want{mode, g.cpl > 1, c.ksplit > 1, tl != nullptr});
     if (!fn) return IQA_ERR_CONFIG;
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     KArgs a{};
-    const size_t bytes = split_ws_bytes(g, c);
-    if (bytes > 0) {
-        st = workspace_for(s, bytes, &a.ws);
+    const SplitNeed need = split_need(g, c);
+    if (need.cnt_bytes > 0) {
+        st = workspace_for(s, need, &a.ws);
         if (st != IQA_OK) return st;
     }
     if (ws == Ws::kPrepare) return IQA_OK;

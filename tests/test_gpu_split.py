@@ -18,14 +18,14 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 
 # (N, NT, ksplit): the default split shapes of the size sweep's large-tile
 # cells, and hand-picked deeper splits (up to one row per workgroup slice).
-SHAPES = [(2048, 256, None), (1024, 256, None), (1024, 512, None), (2048, 128, 8),
-          (512, 512, 128), (256, 64, 16)]
+SHAPES = [(2048, 256, None), (1024, 256, None), (1024, 512, None), (2048, 128, dict(ksplit=8)),
+          (512, 512, dict(waves=1, unroll=4, ksplit=128)), (256, 64, dict(ksplit=16))]
 
 
-def cfg_for(N, NT, ks):
+def cfg_for(N, NT, over):
     cfg = default_cfg(N, NT)
-    if ks is not None:
-        cfg["ksplit"] = ks
+    if over is not None:
+        cfg.update(over)
     assert check_cfg(N, NT, cfg) == 0, (N, NT, cfg)
     return cfg
 
@@ -40,9 +40,9 @@ def run(xd, yd, NT, cfg, stream=None):
     return r
 
 
-@pytest.mark.parametrize("N,NT,ks", SHAPES)
-def test_split_parity_determinism_symmetry(N, NT, ks):
-    cfg = cfg_for(N, NT, ks)
+@pytest.mark.parametrize("N,NT,over", SHAPES)
+def test_split_parity_determinism_symmetry(N, NT, over):
+    cfg = cfg_for(N, NT, over)
     assert cfg["ksplit"] > 1
     rng = np.random.default_rng(N * 7 + NT)
     x, y = synth.random_pair(N, rng, neg_frac=0.3, nan_frac=0.01, scale=1.0)
