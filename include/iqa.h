@@ -88,7 +88,8 @@ typedef enum iqa_status {
                             shape needs more than 2^31-1 workgroups */
     IQA_ERR_CAPTURE = 7, /* workspace would have to grow while the stream is captured */
     IQA_ERR_BUDGET = 8,  /* a request can never fit the server's HBM budget or arena */
-    IQA_ERR_TIMEOUT = 9  /* a server wait ran out of time */
+    IQA_ERR_TIMEOUT = 9, /* a server wait ran out of time */
+    IQA_ERR_SCRATCH = 10 /* the shape needs more split scratch than iqa_tiles_noalloc holds */
 } iqa_status;
 
 /* Largest supported image side: 2^17 pixels (64 GiB per FP32 image). */
@@ -166,6 +167,30 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT,
 /* Workgroups of the single-pair launch for (N, NT) with `cfg` (one per tile
  * group and split part); -1 if the shape or configuration is invalid. */
 int64_t iqa_launch_workgroups(int64_t N, int64_t NT, const iqa_launch_cfg *cfg);
+
+/* Split scratch held by iqa_tiles_noalloc, per GPU: 1 MiB. */
+#define IQA_NOALLOC_SCRATCH_BYTES ((int64_t)1 << 20)
+
+/* iqa_tiles_cfg for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It calls no hipMalloc, hipFree or other allocating routine.  Split shapes
+ * (cfg->ksplit > 1, or a default configuration that splits) take their
+ * partial sums and ticket counters from a fixed array of
+ * IQA_NOALLOC_SCRATCH_BYTES in device memory that the library holds on every
+ * GPU it runs on until the process ends, instead of the per-stream workspace:
+ * 4 bytes per tile group in its first 64 KiB (at most 16384 tile groups) and
+ * 16 bytes per tile and split part in the rest, so a shape needing more
+ * returns IQA_ERR_SCRATCH (launching nothing).  Shapes that do
+ * not split use no scratch.  Results are bitwise those of iqa_tiles_cfg with
+ * the same configuration.  Every call on one GPU shares that GPU's array:
+ * split calls whose launches overlap in time on one GPU (different streams,
+ * or graph replays running concurrently) race and must be avoided; calls
+ * ordered on one stream are safe.  The first call on a device looks up the
+ * array's address (hipGetSymbolAddress) with that device current. */
+iqa_status iqa_tiles_noalloc(const float *x, const float *y, int64_t N, int64_t NT,
+                             float D, float C1, float C2, float C,
+                             float *lisi, float *auglisi, float *sums,
+                             const iqa_launch_cfg *cfg, void *stream);
 
 /* Allocate, ahead of time, the workspace that (N, NT) with `cfg` (NULL =
  * default) needs on `stream`, so that later calls allocate nothing (e.g.

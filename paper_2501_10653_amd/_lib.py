@@ -17,7 +17,7 @@ IQA_OK = 0
 STATUS_NAMES = {
     0: "IQA_OK", 1: "IQA_ERR_NULL", 2: "IQA_ERR_SHAPE", 3: "IQA_ERR_ALIGN",
     4: "IQA_ERR_PARAM", 5: "IQA_ERR_HIP", 6: "IQA_ERR_CONFIG", 7: "IQA_ERR_CAPTURE",
-    8: "IQA_ERR_BUDGET", 9: "IQA_ERR_TIMEOUT",
+    8: "IQA_ERR_BUDGET", 9: "IQA_ERR_TIMEOUT", 10: "IQA_ERR_SCRATCH",
 }
 
 
@@ -88,6 +88,7 @@ BATCH_INLINE_MAX = 16
 TUNE_SINGLE = 0
 TUNE_BATCH = 1
 TUNE_SERVE = 2
+NOALLOC_SCRATCH_BYTES = 1 << 20
 PROBE_READ_REGS = 0
 PROBE_READ_REGS_STRUCT = 1
 PROBE_READ_LDS = 2
@@ -134,6 +135,8 @@ def load() -> ctypes.CDLL:
         "iqa_check_cfg": ([i64, i64, cfgp], ctypes.c_int),
         "iqa_tiles_cfg": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp], ctypes.c_int),
         "iqa_prepare": ([i64, i64, cfgp, vp], ctypes.c_int),
+        "iqa_tiles_noalloc": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp],
+                              ctypes.c_int),
         "iqa_launch_workgroups": ([i64, i64, cfgp], i64),
         "iqa_tiles_timeline": ([vp, vp, i64, i64, f, f, f, f, vp, vp, vp, cfgp, vp, i64, vp],
                                ctypes.c_int),

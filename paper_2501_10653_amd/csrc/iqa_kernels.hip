@@ -1209,6 +1209,38 @@ iqa_status workspace_for(hipStream_t s, const SplitNeed &need, float **part) {
     return IQA_OK;
 }
 
+// Scratch of the no-allocation entry point: a fixed array in device memory,
+// one copy per GPU, held until the process ends.  It starts zeroed (the
+// loader clears the array), and every launch leaves its ticket counters at
+// zero.  Its device address comes from hipGetSymbolAddress, once per device,
+// with that device current; host code never uses the array's name otherwise.
+static __device__ __align__(256) float scratch[IQA_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+// The first kScratchCounterBytes of the array are the counter region (the
+// partial-sum region starts right after it), the rest holds partial sums.
+constexpr size_t kScratchCounterBytes = 64 << 10;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+iqa_status scratch_for_current_device(float **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    if (dev < 0 || dev >= kMaxDevices) return IQA_ERR_CONFIG;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e);
+        if (p == nullptr) return IQA_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<float *>(g_scratch_ptr[dev]);
+    return IQA_OK;
+}
+
 void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, float D,
                float C1, float C2, float C, float *lisi, float *aug, float *sums,
                const iqa_launch_cfg &c, const Geometry &g) {
@@ -1239,6 +1271,7 @@ void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, 
 // Where a launch's split workspace comes from.
 enum class Ws {
     kLibrary,   // the per-(device, stream) buffer, grown on demand
+    kScratch,   // the fixed scratch array (no allocation; bounded size)
     kPrepare,   // only allocate the library buffer, launch nothing
 };
 
@@ -1261,8 +1294,18 @@ iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, f
     KArgs a{};
     const SplitNeed need = split_need(g, c);
     if (need.cnt_bytes > 0) {
-        st = workspace_for(s, need, &a.ws);
-        if (st != IQA_OK) return st;
+        if (ws == Ws::kScratch) {
+            if (need.cnt_bytes > kScratchCounterBytes ||
+                need.part_bytes > IQA_NOALLOC_SCRATCH_BYTES - kScratchCounterBytes)
+                return IQA_ERR_SCRATCH;
+            float *base = nullptr;
+            st = scratch_for_current_device(&base);
+            if (st != IQA_OK) return st;
+            a.ws = reinterpret_cast<float *>(reinterpret_cast<char *>(base) + kScratchCounterBytes);
+        } else {
+            st = workspace_for(s, need, &a.ws);
+            if (st != IQA_OK) return st;
+        }
     }
     if (ws == Ws::kPrepare) return IQA_OK;
 
@@ -1319,6 +1362,16 @@ iqa_status iqa_tiles_cfg(const float *x, const float *y, int64_t N, int64_t NT, 
 iqa_status iqa_tiles(const float *x, const float *y, int64_t N, int64_t NT, float D, float C1,
                      float C2, float C, float *lisi, float *auglisi, float *sums, void *stream) {
     return iqa_tiles_cfg(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, nullptr, stream);
+}
+
+iqa_status iqa_tiles_noalloc(const float *x, const float *y, int64_t N, int64_t NT, float D,
+                             float C1, float C2, float C, float *lisi, float *auglisi, float *sums,
+                             const iqa_launch_cfg *cfg, void *stream) {
+    iqa_status st = check_common(x, y, N, NT);
+    if (st != IQA_OK) return st;
+    st = check_outputs_params(lisi, auglisi, sums, D, C1, C2, C);
+    if (st != IQA_OK) return st;
+    return run(x, y, N, NT, D, C1, C2, C, lisi, auglisi, sums, cfg, stream, Ws::kScratch);
 }
 
 iqa_status iqa_tiles_timeline(const float *x, const float *y, int64_t N, int64_t NT, float D,
@@ -1558,6 +1611,7 @@ const char *iqa_status_str(int status) {
         case IQA_ERR_CAPTURE: return "IQA_ERR_CAPTURE: workspace must grow while the stream is captured";
         case IQA_ERR_BUDGET: return "IQA_ERR_BUDGET: the request can never fit the server's HBM budget";
         case IQA_ERR_TIMEOUT: return "IQA_ERR_TIMEOUT: the wait ran out of time";
+        case IQA_ERR_SCRATCH: return "IQA_ERR_SCRATCH: the shape needs more split scratch than iqa_tiles_noalloc holds";
         default: return "unknown iqa_status";
     }
 }

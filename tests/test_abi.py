@@ -18,7 +18,7 @@ from paper_2501_10653_amd._lib import LaunchCfg
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "iqa.h")
 
-OK, NULL, SHAPE, ALIGN, PARAM, HIP, CONFIG, CAPTURE, BUDGET, TIMEOUT = range(10)
+OK, NULL, SHAPE, ALIGN, PARAM, HIP, CONFIG, CAPTURE, BUDGET, TIMEOUT, SCRATCH = range(11)
 FAKE = 1 << 20          # 16-byte-aligned stand-in for a device pointer (never dereferenced)
 C6 = 1e-6
 
@@ -47,7 +47,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = _lib.load()
-    for s in range(10):
+    for s in range(11):
         assert lib.iqa_status_str(s).decode().startswith(_lib.STATUS_NAMES[s])
     assert b"unknown" in lib.iqa_status_str(99)
     assert lib.iqa_version() >= 100
@@ -310,3 +310,20 @@ def test_missing_library_fails_loudly(tmp_path):
             "sys.exit(1)\n") % (ROOT, str(tmp_path / "missing.so"))
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert res.returncode == 0 and "not built" in res.stdout
+
+
+def test_noalloc_refuses_shapes_beyond_its_scratch_before_any_hip_call():
+    """A split shape whose partial sums exceed the fixed scratch array is
+    refused with IQA_ERR_SCRATCH, and validation errors come first, as for
+    iqa_tiles_cfg."""
+    lib = _lib.load()
+    big = LaunchCfg.from_dict(dict(vec=4, waves=1, unroll=4, seg=64, rp=1, ksplit=64))
+    # 65536^2 / 2048: 1024 tile groups x 64 parts x 16 B = 1 MiB of partials
+    assert lib.iqa_tiles_noalloc(FAKE, FAKE, 65536, 2048, C6 / 2, C6, C6, C6, FAKE, FAKE, None,
+                                 ctypes.byref(big), None) == SCRATCH
+    assert lib.iqa_tiles_noalloc(None, FAKE, 65536, 2048, C6 / 2, C6, C6, C6, FAKE, FAKE, None,
+                                 ctypes.byref(big), None) == NULL
+    assert lib.iqa_tiles_noalloc(FAKE, FAKE, 65536, 2047, C6 / 2, C6, C6, C6, FAKE, FAKE, None,
+                                 None, None) == SHAPE
+    assert lib.iqa_tiles_noalloc(FAKE, FAKE, 2048, 64, C6 / 2, 0.0, C6, C6, FAKE, FAKE, None,
+                                 None, None) == PARAM
