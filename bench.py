@@ -87,6 +87,8 @@ def parse_args(argv=None):
                     help="launches per graph for --workload sweep and readfloor")
     ap.add_argument("--cells", default="",
                     help="--workload sweep: N:NT cells to run (default: all 20)")
+    ap.add_argument("--shape", default="paper",
+                    help="--workload readfloor / timeline: the pair shape (paper, small or N:NT)")
     ap.add_argument("--plan-out", default="",
                     help="write the launch plan (for a rocprofv3 trace summary) to this file")
     return ap.parse_args(argv)
@@ -375,7 +377,7 @@ def run_readfloor(torch, dev, args) -> dict:
     from paper_2501_10653_amd.measure import GraphTimer, Plan, read_floor
     from paper_2501_10653_amd.tune import device_copies
     plan = Plan()
-    spec = workload_spec("paper" if args.workload == "readfloor" else args.workload)
+    spec = workload_spec(args.shape)
     N, NT = spec.N, spec.NT
     nbytes = 8 * N * N
     K = args.sweep_launches
@@ -411,7 +413,7 @@ def run_timeline(torch, dev, args) -> dict:
     from paper_2501_10653_amd import default_cfg, synth
     from paper_2501_10653_amd.measure import timeline
     from paper_2501_10653_amd.tune import device_copies
-    spec = workload_spec("paper" if args.workload == "timeline" else args.workload)
+    spec = workload_spec(args.shape)
     x, y, _ = synth.make_pair(spec)
     nbytes = 8 * spec.N ** 2
     pool = max(2, int(math.ceil(args.pool_bytes / nbytes)))
@@ -430,7 +432,7 @@ def run_sweep(torch, dev, args) -> dict:
     """Every cell of the size sweep (N in 1024..8192, N_T in 16..256) with its
     default launch shape, K launches per graph over >= 1 GiB of distinct
     copies, timed with events (median of 3 replays)."""
-    from paper_2501_10653_amd import default_cfg, iqa_tiles, synth
+    from paper_2501_10653_amd import default_cfg, iqa_tiles, prepare, synth
     from paper_2501_10653_amd.measure import GraphTimer, Plan
     from paper_2501_10653_amd.tune import device_copies
     plan = Plan()
@@ -452,6 +454,7 @@ def run_sweep(torch, dev, args) -> dict:
         xs, ys = pairs[N]
         pool = len(xs)
         cfg = default_cfg(N, NT, xs[0], ys[0])
+        prepare(N, NT, cfg, stream=stream)      # the split workspace, before capture
         ns = N // NT
         out = {"lisi": torch.empty(ns, ns, device=dev),
                "auglisi": torch.empty(ns, ns, device=dev)}
@@ -587,6 +590,15 @@ def main(argv=None) -> int:
 
     K = args.steps
     use_graph = not args.no_graph
+    if args.plan_out:
+        from paper_2501_10653_amd.measure import Plan
+        plan = Plan()
+        kname = "tiles_kernel<"
+        plan.add("warm-up (eager)", kname, args.warmup, bytes=bytes_pair)
+        if use_graph:
+            plan.add("graph replay (untimed)", kname, K, bytes=bytes_pair)
+        plan.add("timed replay", kname, K, bytes=bytes_pair)
+        plan.dump(args.plan_out)
     timer = GraphTimer(torch, dev, stream)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)

@@ -33,11 +33,13 @@
  *   Calls on the same stream are ordered; calls on different streams may run
  *   concurrently.
  * Scratch.  Shapes with few, large tiles split a tile's rows over several
- *   workgroups of one launch; each stores its partial sums and the last one
- *   of a tile to finish adds them in a fixed order and writes the tile's
- *   results (a ticket counter decides which is last; nothing waits).  Those
- *   launches use a small library-owned device workspace per (device, stream)
- *   (16 bytes per tile and split part, plus 4 bytes per tile group),
+ *   workgroups; each stores its partial sums, which are then added in a
+ *   fixed order: by the last of them to finish, within the launch (a ticket
+ *   counter decides which is last; nothing waits), when the launch has at
+ *   most 1024 workgroups, else by a second, small launch on the same stream.
+ *   The two give the same bits.  Those launches use a small library-owned
+ *   device workspace per (device, stream) (16 bytes per tile and split part,
+ *   plus 4 bytes per tile group),
  *   allocated and cleared on first use and reused afterwards (an outgrown
  *   buffer is kept until the process ends, so graphs captured earlier stay
  *   valid).  The first call for a given (device, stream, shape) must
@@ -46,7 +48,8 @@
  * Threads.  Every entry point may be called from several host threads at
  *   once, on the same stream or on different ones.  Calls on one stream run
  *   in the order they were enqueued, each launch finishing before the next
- *   starts, so split launches on one stream share its workspace safely.  A
+ *   starts, and a split call's two launches are enqueued back to back, so
+ *   split launches on one stream share its workspace safely.  A
  *   HIP graph that captured a split-shape launch keeps the capture stream's
  *   workspace: replay it on that stream (or on one stream at a time, with
  *   nothing else using that workspace meanwhile), because two split launches
@@ -135,8 +138,9 @@ iqa_status auglisi_tiles(const float *x, const float *y, int64_t N, int64_t NT,
  * row in `vec`-float loads and `rp` such segments take interleaved rows, so a
  * wave covers ht = 64/(seg*rp) adjacent tiles and reduces them without LDS.
  * A workgroup of `waves` waves splits those tiles' rows into contiguous
- * slices (combined in LDS); `ksplit` workgroups split them further (the last
- * of them to finish combines their partial sums).  `unroll` rows per lane are loaded
+ * slices (combined in LDS); `ksplit` workgroups split them further (their
+ * partial sums are added by the last of them to finish, or by a second
+ * launch for launches of more than 1024 workgroups).  `unroll` rows per lane are loaded
  * while the previous `unroll` are reduced. */
 typedef struct iqa_launch_cfg {
     int32_t vec;     /* floats per lane load: 4, 2 or 1; NT % vec == 0 */
@@ -185,7 +189,7 @@ int64_t iqa_launch_workgroups(int64_t N, int64_t NT, const iqa_launch_cfg *cfg);
  * the same configuration.  Every call on one GPU shares that GPU's array:
  * split calls whose launches overlap in time on one GPU (different streams,
  * or graph replays running concurrently) race and must be avoided; calls
- * ordered on one stream are safe.  The first call on a device looks up the
+ * ordered on one stream, from any number of host threads, are safe.  The first call on a device looks up the
  * array's address (hipGetSymbolAddress) with that device current. */
 iqa_status iqa_tiles_noalloc(const float *x, const float *y, int64_t N, int64_t NT,
                              float D, float C1, float C2, float C,
@@ -471,7 +475,9 @@ iqa_status iqa_read_ceiling(const float *buf, int64_t n, float *out, int64_t blo
  *                first loads back), of its last rows reduced (its last loads
  *                back) and of its exit once its results were stored; then the
  *                XCC_ID and HW_ID hardware registers it ran with, its tile
- *                group and split part.
+ *                group, and its split part with bit 32 set when this
+ *                workgroup finished its tiles (always, without a split; for
+ *                the part that came last, with one).
  * The stamps cost a few instructions per workgroup; the product entry points
  * are separate kernels without them. */
 iqa_status iqa_tiles_timeline(const float *x, const float *y, int64_t N, int64_t NT, float D,

@@ -50,11 +50,14 @@ namespace iqa {
 
 constexpr int kWave = 64;
 enum Mode : int { kLisi = 1, kAug = 2, kBoth = 3 };
+// How the parts of a split tile group are added up (see split_finish).
+enum SplitMode : int { kSplitNone = 0, kSplitTicket = 1, kSplitCombine = 2 };
 
 struct KArgs {
     const float *x;
     const float *y;
-    int64_t N;           // image side (row stride in floats)
+    int32_t N;           // image side (row stride in floats), <= 2^17
+    int32_t smode;       // split tiles: kSplitNone, kSplitTicket or kSplitCombine
     int32_t NT;          // tile side
     int32_t ns;          // tiles per side
     int32_t ngx;         // tile groups along x: ceil(ns / ht)
@@ -507,33 +510,43 @@ __device__ __forceinline__ float4 wave_tree(float4 (&v)[WAVES]) {
 }
 
 // ---------------------------------------------------------------------------
-// Split tiles: the last part to arrive finishes the tile group
+// Split tiles: adding up the parts of a tile group
 // ---------------------------------------------------------------------------
 //
 // With ks > 1 workgroups per tile group, every part stores its partial sums
-// (one float4 per tile) and then takes a ticket from the group's counter.
-// The part that draws the last ticket has seen every other part's partials:
-// it adds them and finalises, and sets the counter back to zero for the next
-// launch.  No part waits for another.
+// (one float4 per tile), and the parts are added in one of two ways:
 //
-// The parts run on different XCDs, whose L2 caches are not coherent with one
-// another, so the partials travel by device-coherent accesses (agent-scope
-// atomic stores and loads, which bypass the non-coherent cache levels), and
-// only the ordering is left to the counter: a part's partial stores have
-// completed (vmcnt 0) before it takes its ticket, and the last part issues
-// its partial loads only after its ticket has returned.
+//   * kSplitTicket: each part then takes a ticket from the group's counter,
+//     and the part that draws the last one adds the partials and finalises,
+//     within the same launch; it also sets the counter back to zero.  No part
+//     waits for another.  The parts run on different XCDs, whose L2 caches
+//     are not coherent with one another, so the partials travel by
+//     device-coherent accesses (agent-scope atomic stores and loads, which
+//     bypass the non-coherent cache levels), and only the ordering is left to
+//     the counter: a part's partial stores have completed (vmcnt 0) before it
+//     takes its ticket, and the last part issues its partial loads only after
+//     its ticket has returned.
+//   * kSplitCombine: the parts only store their partials, and combine_kernel,
+//     launched right after on the same stream, adds them.
 //
-// The last part adds the partials the way the kernel adds pixels: lane q of
+// The ticket costs every part a few memory round trips at its end (store
+// acknowledgement, atomic); while a launch fits the GPU in one round of
+// workgroups that is cheaper than a second launch, but when many rounds of
+// workgroups queue behind those round trips it is not, and the host picks
+// the combine launch (split_mode).
+//
+// Either way the partials are added the way the kernel adds pixels: lane q of
 // tile j's lane group Kahan-adds parts q, q + g, q + 2g, ... (g lanes per
 // tile), then the group is summed with the same fixed DPP tree.  The order
-// does not depend on which part came last, so results are bitwise
-// reproducible.
+// depends neither on the mechanism nor on which part came last, so results
+// are bitwise reproducible and equal between the two.
 //
-// Workspace: partials [group][part][ht] float4 from a.ws on, and one 32-bit
-// counter per group just below a.ws (group g's at a.ws - 4 (g + 1) bytes), in
-// a counter region that holds nothing but counters.  The counters start at
-// zero and every launch leaves the ones it used at zero, so a region reused by
-// shapes of any size is all zeros between launches.
+// Workspace: partials [group][part][ht] float4 from a.ws on, and (ticket
+// mode) one 32-bit counter per group just below a.ws (group g's at
+// a.ws - 4 (g + 1) bytes), in a counter region that holds nothing but
+// counters.  The counters start at zero and every launch leaves the ones it
+// used at zero, so a region reused by shapes of any size is all zeros between
+// launches.
 __host__ __device__ __forceinline__ int64_t split_partials(int64_t groups, int64_t ks, int64_t ht) {
     return groups * ks * ht;   // float4 entries
 }
@@ -559,22 +572,16 @@ __device__ __forceinline__ void wait_vmem() {
     __builtin_amdgcn_s_waitcnt(/*vmcnt*/ 0 | (/*expcnt*/ 0x7 << 4) | (/*lgkmcnt*/ 0xf << 8));
 }
 
-template <int MODE>
-__device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, int lane, bool mine,
-                                             int jt, int ty, int txg, float4 v) {
-    float4 *ws = reinterpret_cast<float4 *>(a.ws);
+// Add up tile group grp's parts and finalise its tiles (one wave).  COHERENT
+// reads the partials with device-coherent loads (within the launch that wrote
+// them), else with plain loads (a later launch).
+template <int MODE, bool COHERENT>
+__device__ __forceinline__ void combine_parts(const KArgs &a, int grp, int lane) {
+    const float4 *ws = reinterpret_cast<const float4 *>(a.ws);
     const int64_t base = (int64_t)grp * a.ks;
-    if (mine) store_coherent(ws + (base + part) * a.ht + jt, v);
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(a.ws) - 1 - grp;
-    wait_vmem();                                        // partials stored before the ticket
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    uint32_t ticket = 0;
-    if (lane == 0) ticket = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ticket = __builtin_amdgcn_readfirstlane(ticket);    // waits for the returned value
-    if (ticket != (uint32_t)(a.ks - 1)) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-
-    // Lane group of tile j: 2^log_grp lanes, lane q of the group takes parts
+    const int ty = udiv(grp, a.ngx_m, a.ngx);
+    const int txg = grp - ty * a.ngx;
+    // Lane group of tile j: 2^log_grp lanes; lane q of the group takes parts
     // q, q + g, ...
     const int g = 1 << a.log_grp;
     const int j = lane >> a.log_grp;
@@ -583,7 +590,8 @@ __device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, 
     Acc c = acc_zero();
     if (tx < a.ns) {
         for (int p = q; p < a.ks; p += g) {
-            const float4 w = load_coherent(ws + (base + p) * a.ht + j);
+            const float4 *src = ws + (base + p) * a.ht + j;
+            const float4 w = COHERENT ? load_coherent(src) : *src;
             if constexpr ((MODE & kLisi) != 0) cadd(c.A, w.x);
             if constexpr ((MODE & kAug) != 0) cadd(c.P, w.y);
             cadd(c.X, w.z);
@@ -592,7 +600,31 @@ __device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, 
     }
     const Sum4 s = group_allreduce<MODE>(fold(c), a.log_grp);
     if (q == 0 && tx < a.ns) finalize<MODE>(a, (int64_t)ty * a.ns + tx, acc_of(s));
+}
+
+// A part's end of a split tile group; returns whether this workgroup
+// finished the group (ticket mode, last part).
+template <int MODE>
+__device__ __forceinline__ bool split_finish(const KArgs &a, int grp, int part, int lane, bool mine,
+                                             int jt, float4 v) {
+    float4 *ws = reinterpret_cast<float4 *>(a.ws);
+    float4 *slot = ws + ((int64_t)grp * a.ks + part) * a.ht + jt;
+    if (a.smode == kSplitCombine) {
+        if (mine) *slot = v;
+        return false;
+    }
+    if (mine) store_coherent(slot, v);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(a.ws) - 1 - grp;
+    wait_vmem();                                        // partials stored before the ticket
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t ticket = 0;
+    if (lane == 0) ticket = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);    // waits for the returned value
+    if (ticket != (uint32_t)(a.ks - 1)) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    combine_parts<MODE, true>(a, grp, lane);
     if (lane == 0) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -610,7 +642,8 @@ __device__ __forceinline__ void split_finish(const KArgs &a, int grp, int part, 
 // wave 0: entry, its first batch of rows reduced (first loads back), its last
 // rows reduced (last loads back), and its exit after the results are stored,
 // plus the XCD and hardware slot it ran on: 8 uint64 per workgroup at
-// tl[8 * blockIdx.x], written with ordinary vector stores.
+// tl[8 * blockIdx.x], written with ordinary vector stores; the split part's
+// word has bit 32 set when this workgroup finished its tiles.
 template <int VEC, int WAVES, int U, int MODE, bool WIDE, bool SPLIT, bool TL>
 __device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
     uint64_t ts[4] = {0, 0, 0, 0};
@@ -648,11 +681,12 @@ __device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
             v = wave_tree<WAVES>(w);
         }
     }
+    bool last = true;   // this workgroup finished its tiles
     if constexpr (!SPLIT) {
         if (mine) finalize<MODE>(a, (int64_t)ty * a.ns + txg * a.ht + jt,
                                  acc_of(Sum4{v.x, v.y, v.z, v.w}));
     } else {
-        split_finish<MODE>(a, grp, part, lane, mine, jt, ty, txg, v);
+        last = split_finish<MODE>(a, grp, part, lane, mine, jt, v);
     }
     if constexpr (TL) {
         if (wave == 0) {
@@ -667,7 +701,7 @@ __device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
                 r[4] = (uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 20);   // XCC_ID
                 r[5] = (uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
                 r[6] = (uint64_t)grp;
-                r[7] = (uint64_t)part;
+                r[7] = (uint64_t)part | ((uint64_t)last << 32);
             }
         }
     }
@@ -681,6 +715,13 @@ __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel(KArgs a) {
 template <int VEC, int WAVES, int U, bool WIDE, bool SPLIT>
 __global__ __launch_bounds__(WAVES * kWave) void tiles_kernel_tl(KArgs a, uint64_t *tl) {
     tiles_body<VEC, WAVES, U, kBoth, WIDE, SPLIT, true>(a, tl);
+}
+
+// kSplitCombine: one wave per tile group adds its parts, after the tile
+// kernel on the same stream (so the partials are complete and visible).
+template <int MODE>
+__global__ __launch_bounds__(kWave) void combine_kernel(KArgs a) {
+    combine_parts<MODE, false>(a, (int)blockIdx.x, (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,14 +1202,26 @@ std::mutex g_ws_mutex;
 std::map<std::pair<int, void *>, Workspace> g_ws;
 std::vector<void *> g_ws_retired;
 
+// Split launches of at most this many workgroups (one round on gfx950's 256
+// CUs at four workgroups each) add their parts by ticket, within the launch;
+// larger ones store their partials and a combine launch adds them (see
+// split_finish for why).
+constexpr int64_t kTicketMaxGrid = 1024;
+
+int split_mode(const Geometry &g, const iqa_launch_cfg &c) {
+    if (c.ksplit <= 1) return kSplitNone;
+    return g.grid <= kTicketMaxGrid ? kSplitTicket : kSplitCombine;
+}
+
 struct SplitNeed {
     size_t cnt_bytes = 0, part_bytes = 0;   // 0, 0: the launch does not split
 };
 
 SplitNeed split_need(const Geometry &g, const iqa_launch_cfg &c) {
     SplitNeed n;
-    if (c.ksplit <= 1) return n;
-    n.cnt_bytes = (size_t)g.groups * sizeof(uint32_t);
+    const int m = split_mode(g, c);
+    if (m == kSplitNone) return n;
+    if (m == kSplitTicket) n.cnt_bytes = (size_t)g.groups * sizeof(uint32_t);
     n.part_bytes = (size_t)split_partials(g.groups, c.ksplit, g.ht) * 4 * sizeof(float);
     return n;
 }
@@ -1176,12 +1229,11 @@ SplitNeed split_need(const Geometry &g, const iqa_launch_cfg &c) {
 size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
 // *part receives the partial-sum region; the counter region ends where it
-// starts.
+// starts.  The caller holds g_ws_mutex.
 iqa_status workspace_for(hipStream_t s, const SplitNeed &need, float **part) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_status(e);
-    std::lock_guard<std::mutex> lock(g_ws_mutex);
     Workspace &w = g_ws[{dev, (void *)s}];
     if (w.cnt_bytes < need.cnt_bytes || w.part_bytes < need.part_bytes) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1224,12 +1276,12 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
 void *g_scratch_ptr[kMaxDevices] = {};
 
+// The caller holds g_scratch_mutex.
 iqa_status scratch_for_current_device(float **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_status(e);
     if (dev < 0 || dev >= kMaxDevices) return IQA_ERR_CONFIG;
-    std::lock_guard<std::mutex> lock(g_scratch_mutex);
     if (g_scratch_ptr[dev] == nullptr) {
         void *p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
@@ -1246,7 +1298,8 @@ void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, 
                const iqa_launch_cfg &c, const Geometry &g) {
     a.x = x;
     a.y = y;
-    a.N = N;
+    a.N = (int32_t)N;
+    a.smode = kSplitNone;
     a.NT = (int32_t)NT;
     a.ns = (int32_t)g.ns;
     a.ngx = (int32_t)g.ngx;
@@ -1266,6 +1319,13 @@ void fill_args(KArgs &a, const float *x, const float *y, int64_t N, int64_t NT, 
     a.lisi = lisi;
     a.aug = aug;
     a.sums = sums;
+}
+
+hipError_t launch_combine(const KArgs &a, int mode, const Geometry &g, hipStream_t s) {
+    void (*fn)(KArgs) = mode == kLisi  ? &combine_kernel<kLisi>
+                        : mode == kAug ? &combine_kernel<kAug>
+                                       : &combine_kernel<kBoth>;
+    return launch_kernel(fn, (unsigned)g.groups, kWave, s, a);
 }
 
 // Where a launch's split workspace comes from.
@@ -1293,16 +1353,23 @@ iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, f
 
     KArgs a{};
     const SplitNeed need = split_need(g, c);
-    if (need.cnt_bytes > 0) {
+    // The workspace (or scratch) stays locked until the launches are
+    // enqueued: a combine-mode split is two launches, and another host
+    // thread's split launches on the same stream must not come between them.
+    std::unique_lock<std::mutex> ws_lock(g_ws_mutex, std::defer_lock);
+    std::unique_lock<std::mutex> scratch_lock(g_scratch_mutex, std::defer_lock);
+    if (need.part_bytes > 0) {
         if (ws == Ws::kScratch) {
             if (need.cnt_bytes > kScratchCounterBytes ||
                 need.part_bytes > IQA_NOALLOC_SCRATCH_BYTES - kScratchCounterBytes)
                 return IQA_ERR_SCRATCH;
+            scratch_lock.lock();
             float *base = nullptr;
             st = scratch_for_current_device(&base);
             if (st != IQA_OK) return st;
             a.ws = reinterpret_cast<float *>(reinterpret_cast<char *>(base) + kScratchCounterBytes);
         } else {
+            ws_lock.lock();
             st = workspace_for(s, need, &a.ws);
             if (st != IQA_OK) return st;
         }
@@ -1310,7 +1377,10 @@ iqa_status run(const float *x, const float *y, int64_t N, int64_t NT, float D, f
     if (ws == Ws::kPrepare) return IQA_OK;
 
     fill_args(a, x, y, N, NT, D, C1, C2, C, lisi, aug, sums, c, g);
-    return hip_status(fn(a, tl, (unsigned)g.grid, s));
+    a.smode = split_mode(g, c);
+    hipError_t e = fn(a, tl, (unsigned)g.grid, s);
+    if (e == hipSuccess && a.smode == kSplitCombine) e = launch_combine(a, mode, g, s);
+    return hip_status(e);
 }
 
 iqa_status check_common(const float *x, const float *y, int64_t N, int64_t NT) {

@@ -214,6 +214,11 @@ def timeline(torch, dev, xs, ys, NT: int, cfg: dict, launches: int = 64) -> Dict
     wg_busy = np.median(end - entry, axis=1) * tick_us
     xcc = st[0, :, 4].astype(np.int64) & 0xF
     per_xcd = np.bincount(xcc, minlength=8).tolist()
+    fin = (st[:, :, 7].astype(np.int64) >> 32) == 1
+    # a finishing workgroup's exit after its own last data, against the others'
+    fin_tail = np.nanmedian(np.where(fin, end - last, np.nan), axis=1) * tick_us
+    other_tail = np.nanmedian(np.where(~fin, end - last, np.nan), axis=1) * tick_us \
+        if (~fin).any() else None
     bytes_launch = 8 * N * N
 
     def stat(a):
@@ -234,6 +239,8 @@ def timeline(torch, dev, xs, ys, NT: int, cfg: dict, launches: int = 64) -> Dict
         "gap_to_next_launch_us": stat(gaps) if gaps.size else None,
         "workgroup_busy_us": stat(wg_busy),
         "workgroups_per_xcd": per_xcd,
+        "finishing_wg_exit_after_data_us": stat(fin_tail),
+        "other_wg_exit_after_data_us": stat(other_tail) if other_tail is not None else None,
         "data_phase_GBs": round(bytes_launch / np.median(data_end) / 1e3, 1),
         "span_GBs": round(bytes_launch / span_med / 1e3, 1),
         "ideal_us_at_peak": round(bytes_launch / HBM_PEAK_GBS / 1e3, 3),

@@ -62,33 +62,16 @@ def candidates_single(N: int, NT: int, max_waves_total: int = 1 << 17) -> List[d
 
 
 class _Timer:
-    """Graph-replay timing on one stream with a rotating pool of pairs."""
+    """Graph-replay timing on one stream with a rotating pool of pairs: the
+    measurement harness's rule (K launches in one graph, an untimed replay,
+    then timed replays each behind a read-only prelude)."""
 
     def __init__(self, torch, stream):
-        self.torch = torch
-        self.stream = stream
+        from .measure import GraphTimer
+        self.timer = GraphTimer(torch, torch.device("cuda", torch.cuda.current_device()), stream)
 
     def per_launch_us(self, launch, K: int, reps: int = 5) -> float:
-        torch = self.torch
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=self.stream):
-            for i in range(K):
-                launch(i)
-        with torch.cuda.stream(self.stream):
-            g.replay()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        ts = []
-        for _ in range(reps):
-            e0.record(self.stream)
-            with torch.cuda.stream(self.stream):
-                g.replay()
-            e1.record(self.stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1) / K * 1e3)
-        del g
-        return float(np.median(ts))
+        return self.timer.per_launch_us(launch, K, reps=reps)
 
 
 def evict_infinity_cache(torch, dev, nbytes: int = 512 << 20, passes: int = 4) -> None:
@@ -329,7 +312,7 @@ def main(argv=None) -> int:
         print(msg, flush=True)
 
     for N, NT in shapes:
-        cfg, us, res = tune_single(N, NT, K=args.K)
+        cfg, us, res = tune_single(N, NT, K=args.K, log=log)
         doc["single"][f"{N}x{NT}"] = {"cfg": cfg, "us": round(us, 3),
                                       "gbs": round(8 * N * N / us / 1e3, 1),
                                       "runner_up": [{"cfg": c, "us": round(u, 3)}

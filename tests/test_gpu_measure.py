@@ -39,7 +39,11 @@ def test_timeline_matches_product_launch(N, NT, ks):
     assert (entry > 0).all()
     assert (entry <= first).all() and (first <= last).all() and (last <= end).all()
     assert (end - entry).max() < _lib.load().iqa_wall_clock_khz() * 10   # under 10 ms
-    assert sorted(st[:, 6] * cfg["ksplit"] + st[:, 7]) == list(range(nwg))
+    part = st[:, 7] & 0xFFFFFFFF
+    last = st[:, 7] >> 32
+    assert sorted(st[:, 6] * cfg["ksplit"] + part) == list(range(nwg))
+    # exactly one finishing workgroup per tile group
+    assert sorted(st[last == 1, 6]) == list(range(nwg // cfg["ksplit"]))
 
 
 def test_probe_read_sums_what_it_reads():

@@ -1,6 +1,8 @@
-"""Split shapes (several workgroups per tile group, the last one to finish
-adds the parts' partial sums): determinism, symmetry, concurrent callers on
-one stream, and graph replays, against single runs and the oracle."""
+"""Split shapes (several workgroups per tile group): determinism, symmetry,
+concurrent callers on one stream, and graph replays, against single runs and
+the oracle.  Launches of at most 1024 workgroups add their parts by ticket
+(the last part to finish adds them); larger ones through a second, combine
+launch; both mechanisms are covered."""
 
 from __future__ import annotations
 
@@ -18,8 +20,12 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 
 # (N, NT, ksplit): the default split shapes of the size sweep's large-tile
 # cells, and hand-picked deeper splits (up to one row per workgroup slice).
+TICKET_MAX_GRID = 1024
+COMBINE = dict(waves=1, unroll=8, ksplit=8)      # 2048^2/128: 2048 workgroups
 SHAPES = [(2048, 256, None), (1024, 256, None), (1024, 512, None), (2048, 128, dict(ksplit=8)),
-          (512, 512, dict(waves=1, unroll=4, ksplit=128)), (256, 64, dict(ksplit=16))]
+          (512, 512, dict(waves=1, unroll=4, ksplit=128)), (256, 64, dict(ksplit=16)),
+          (2048, 128, COMBINE), (4096, 128, dict(waves=1, unroll=8, ksplit=4)),
+          (1024, 64, dict(waves=1, unroll=4, ksplit=4))]
 
 
 def cfg_for(N, NT, over):
@@ -56,13 +62,21 @@ def test_split_parity_determinism_symmetry(N, NT, over):
     assert same(a.lisi, c.lisi) and same(a.auglisi, c.auglisi)
 
 
+def test_both_mechanisms_are_covered():
+    from paper_2501_10653_amd.iqa import launch_workgroups
+    grids = [launch_workgroups(N, NT, cfg_for(N, NT, over)) for N, NT, over in SHAPES]
+    assert min(grids) <= TICKET_MAX_GRID < max(grids)
+
+
 @pytest.mark.parametrize("use_null_stream", [False, True])
-def test_two_threads_share_one_stream(use_null_stream):
+@pytest.mark.parametrize("NT,over", [(256, None), (128, COMBINE)])
+def test_two_threads_share_one_stream(use_null_stream, NT, over):
     """Two host threads issue split launches with different inputs on one
     shared stream (a torch stream, or the legacy NULL stream) as fast as they
-    can; every result equals the same launch run alone, bitwise."""
-    N, NT = 2048, 256
-    cfg = cfg_for(N, NT, None)
+    can; every result equals the same launch run alone, bitwise (a combine
+    launch never reads another call's partials)."""
+    N = 2048
+    cfg = cfg_for(N, NT, over)
     rng = np.random.default_rng(99)
     inputs = []
     for _ in range(2):

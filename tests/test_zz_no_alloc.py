@@ -45,6 +45,7 @@ def call(fn, xd, yd, NT, cfg, stream):
     [(2048, 256, None), (1024, 256, None)],      # default split shapes, second smaller
     [(1024, 512, 32), (512, 512, 8)],            # deep split, then a shallower smaller one
     [(2048, 64, None), (256, 32, None)],         # no split: no scratch used
+    [(2048, 128, 8), (1024, 128, 8)],            # one wave per workgroup: combine launches
 ])
 def test_noalloc_equals_allocating_entry_point(shapes):
     lib = _lib.load()
@@ -56,6 +57,8 @@ def test_noalloc_equals_allocating_entry_point(shapes):
         cfg = default_cfg(N, NT, xd, yd)
         if ks is not None:
             cfg["ksplit"] = ks
+            if NT == 128 and ks == 8:
+                cfg.update(waves=1, unroll=8)
         print(f"noalloc N={N} NT={NT} cfg={cfg}", flush=True)
         st0, l0, a0, s0 = call(lib.iqa_tiles_cfg, xd, yd, NT, cfg, s)
         st1, l1, a1, s1 = call(lib.iqa_tiles_noalloc, xd, yd, NT, cfg, s)
