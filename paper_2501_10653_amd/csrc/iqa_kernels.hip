@@ -1124,6 +1124,15 @@ static const int64_t kTunedBatchWaves = 0;
 std::mutex g_tune_mutex;
 std::map<std::tuple<int64_t, int64_t, int>, iqa_launch_cfg> g_tuned;
 
+// The per-pair geometries the batch kernel can run: vec 4, no row split,
+// unroll 8, and one wave per tile group or the workgroup's four waves on each.
+constexpr int kBatchUnroll = 8;
+
+bool batch_geometry_ok(const iqa_launch_cfg &c) {
+    return c.vec == 4 && c.ksplit == 1 && c.unroll == kBatchUnroll &&
+           (c.waves == 1 || c.waves == kBatchWaves);
+}
+
 bool tuned_lookup(int64_t N, int64_t NT, int kind, iqa_launch_cfg *out) {
     {
         std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -1141,6 +1150,7 @@ bool tuned_lookup(int64_t N, int64_t NT, int kind, iqa_launch_cfg *out) {
             if (e.N == n && e.NT == NT && e.kind == kind) {
                 Geometry g{};
                 if (geometry(N, NT, e.cfg, g) != IQA_OK) continue;
+                if (kind != IQA_TUNE_SINGLE && !batch_geometry_ok(e.cfg)) continue;
                 *out = e.cfg;
                 return true;
             }
@@ -1157,7 +1167,6 @@ iqa_launch_cfg pick_cfg(int64_t N, int64_t NT, const float *x, const float *y) {
 
 // Per-pair geometry inside a batch: vec 4, one wave per tile group, no row
 // split, and as many tiles per wave as make a unit of about 64 KiB of input.
-constexpr int kBatchUnroll = 8;
 
 iqa_launch_cfg batch_cfg(int64_t N, int64_t NT) {
     iqa_launch_cfg c;
@@ -1527,10 +1536,7 @@ iqa_status iqa_tune_set(int64_t N, int64_t NT, int kind, const iqa_launch_cfg *c
     st = geometry(N == 0 ? NT : N, NT, *cfg, g);
     if (st != IQA_OK) return st;
     if (cfg->vec != 4) return IQA_ERR_CONFIG;
-    if (kind != IQA_TUNE_SINGLE &&
-        ((cfg->waves != 1 && cfg->waves != kBatchWaves) || cfg->ksplit != 1 ||
-         cfg->unroll != kBatchUnroll))
-        return IQA_ERR_CONFIG;
+    if (kind != IQA_TUNE_SINGLE && !batch_geometry_ok(*cfg)) return IQA_ERR_CONFIG;
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tuned[std::make_tuple(N, NT, kind)] = *cfg;
     return IQA_OK;

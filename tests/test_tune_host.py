@@ -85,3 +85,23 @@ def test_serving_geometry_covers_the_served_shapes():
         key = f"{N}x{NT}"
         assert key in doc.get("serve", {}), key
         assert serve_cfg(N, NT) == {k: int(v) for k, v in doc["serve"][key].items()}, key
+
+
+def test_batch_entries_outside_the_batch_geometry_are_refused(tmp_path):
+    """A hand-edited cache with a batch or server entry the batch kernel cannot
+    run (two waves per tile group, a row split, unroll 4) does not build, and
+    the library refuses the same entry at run time."""
+    import ctypes
+    import pytest
+    from paper_2501_10653_amd import _lib
+    from paper_2501_10653_amd._lib import LaunchCfg
+    good = dict(vec=4, waves=1, unroll=8, seg=16, rp=2, ksplit=1)
+    for bad in (dict(good, waves=2), dict(good, ksplit=2), dict(good, unroll=4),
+                dict(good, vec=2)):
+        for section, key in (("batch", "64"), ("serve", "1024x64")):
+            src = tmp_path / "cache.json"
+            src.write_text(json.dumps({section: {key: bad}}))
+            with pytest.raises(ValueError):
+                build.write_tuned_table(str(src), str(tmp_path / "t.inc"))
+        assert _lib.load().iqa_tune_set(1024, 64, _lib.TUNE_BATCH,
+                                        ctypes.byref(LaunchCfg.from_dict(bad))) == 6
