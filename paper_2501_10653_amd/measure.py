@@ -283,14 +283,61 @@ def trace_summary(trace_csv: str, plan_json: str) -> List[dict]:
     return out
 
 
+# ---------------------------------------------------------------------------
+# HBM traffic from rocprofv3 counters
+# ---------------------------------------------------------------------------
+
+CALIBRATION_KERNEL = "copyBuffer"     # the runtime's device-to-device copy
+CALIBRATION_BYTES = 256 << 20         # bench.py --profile copies 256 MiB, 3 times
+
+
+def _counter_rows(path: str, kernel: str) -> List[float]:
+    import csv
+    with open(path) as fh:
+        return [float(r["Counter_Value"]) for r in csv.DictReader(fh) if kernel in r["Kernel_Name"]]
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, algorithmic_bytes: int) -> Dict:
+    """HBM bytes per launch of `kernel` from one FETCH_SIZE and one WRITE_SIZE
+    counter pass (KiB per dispatch), each scaled by what the same counter
+    reads for the run's 256 MiB device copies (the largest copyBuffer
+    dispatches): bytes = KiB * 1024 * (copy bytes / copy KiB counted)."""
+    out = {}
+    for name, path, copy_kib_true in (("fetch", fetch_csv, CALIBRATION_BYTES / 1024),
+                                      ("write", write_csv, CALIBRATION_BYTES / 1024)):
+        k = _counter_rows(path, kernel)
+        cal = sorted(_counter_rows(path, CALIBRATION_KERNEL))[-3:]
+        if not k or not cal:
+            raise ValueError(f"{path}: no {kernel} or calibration dispatches")
+        scale = copy_kib_true / (sum(cal) / len(cal))
+        out[f"{name}_kib_per_dispatch"] = round(sum(k) / len(k), 2)
+        out[f"{name}_dispatches"] = len(k)
+        out[f"{name}_scale"] = round(scale, 4)
+    hbm = (out["fetch_kib_per_dispatch"] * out["fetch_scale"] +
+           out["write_kib_per_dispatch"] * out["write_scale"]) * 1024
+    out["hbm_bytes_per_launch"] = int(round(hbm))
+    out["algorithmic_bytes_per_launch"] = int(algorithmic_bytes)
+    out["ratio"] = round(hbm / algorithmic_bytes, 5)
+    return out
+
+
 def main(argv=None) -> int:
     import argparse
     ap = argparse.ArgumentParser(description="Summarise a rocprofv3 kernel trace against a "
-                                             "launch plan written by bench.py")
-    ap.add_argument("--trace", required=True, help="rocprofv3 *_kernel_trace.csv")
-    ap.add_argument("--plan", required=True, help="plan JSON written by bench.py --plan-out")
+                                             "launch plan written by bench.py, or turn two "
+                                             "counter passes into HBM bytes per launch")
+    ap.add_argument("--trace", help="rocprofv3 *_kernel_trace.csv")
+    ap.add_argument("--plan", help="plan JSON written by bench.py --plan-out")
     ap.add_argument("--all", action="store_true", help="also list the untimed (warm) segments")
+    ap.add_argument("--fetch", help="FETCH_SIZE *_counter_collection.csv")
+    ap.add_argument("--write", help="WRITE_SIZE *_counter_collection.csv")
+    ap.add_argument("--kernel", default="tiles_kernel")
+    ap.add_argument("--algorithmic-bytes", type=int, default=0)
     args = ap.parse_args(argv)
+    if args.fetch:
+        print(json.dumps(traffic(args.fetch, args.write, args.kernel, args.algorithmic_bytes),
+                         indent=1))
+        return 0
     recs = trace_summary(args.trace, args.plan)
     print("| segment | dispatches | median ns | min ns | p90 ns | mean ns | GB/s (median) "
           "| % of 8 TB/s |")
