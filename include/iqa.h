@@ -64,7 +64,7 @@
  * Precision.  Per-pixel terms are FP32; tile sums are Kahan-compensated FP32;
  *   augLISI is finalised in double-float arithmetic; the final quotients are
  *   within one unit in the last place.  Worst-case error against exact
- *   arithmetic: about 3.3e-6 (55 units of FP32 roundoff) relative to the
+ *   arithmetic: about 3.6e-6 (61 units of FP32 roundoff) relative to the
  *   value for the sums and LISI, and relative to max(|augLISI|,
  *   P/(Sx+Sy+C)) for augLISI; measured: below 6e-7.  Results are bitwise
  *   reproducible run to run for a given launch configuration (no floating-point
