@@ -98,6 +98,64 @@ hipError_t launch_publish(const Slot &s) {
 // it failed (a failed batch never publishes).
 constexpr int64_t kErrorCheckNs = 1000000;
 
+// The first launch of a kernel in a process, and the first work on a new
+// stream, can hold the device for milliseconds; left to the first requests,
+// that shows as a burst of millisecond latencies at the start of a server's
+// life.  At creation the server therefore runs every launch form it can use
+// once, on a tiny zero pair, and waits for it: the batch kernel with 1, 4 and
+// IQA_BATCH_INLINE_MAX descriptors in its arguments and with a descriptor
+// table (as far as max_batch allows), and the publishing kernel on every slot
+// stream (storing 0, the word's initial value).  Returns the first HIP error.
+hipError_t warm_up(std::vector<Slot> &slots, const iqa_server_opts &o) {
+    constexpr int64_t kN = 32;   // one 32 x 32 tile per pair
+    constexpr int64_t kPairs = IQA_BATCH_INLINE_MAX + 1;
+    const int64_t img = kN * kN;
+    float *buf = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&buf),
+                             (size_t)(img + 2 * kPairs) * sizeof(float));
+    if (e != hipSuccess) return e;
+    Slot &s0 = slots[0];
+    e = hipMemsetAsync(buf, 0, (size_t)img * sizeof(float), s0.stream);
+    const int64_t counts[] = {1, 4, IQA_BATCH_INLINE_MAX, IQA_BATCH_INLINE_MAX + 1};
+    int64_t prev = 0;
+    for (int64_t c : counts) {
+        c = std::min<int64_t>(c, o.max_batch);
+        if (e != hipSuccess || c == prev) continue;
+        prev = c;
+        std::vector<iqa_pair> pairs((size_t)c);
+        for (int64_t i = 0; i < c; ++i)
+            pairs[(size_t)i] = iqa_pair{buf, buf, kN, kN, o.D, o.C1, o.C2, o.C,
+                                        buf + img + 2 * i, buf + img + 2 * i + 1, nullptr};
+        int64_t units = 0;
+        // Constants a request could not use either: nothing to warm up.
+        if (iqa::describe_pairs(pairs.data(), c, s0.desc_host, &units, IQA_TUNE_SERVE) != IQA_OK)
+            break;
+        iqa_status st;
+        if (c <= IQA_BATCH_INLINE_MAX) {
+            st = iqa_tiles_batched_inline(s0.desc_host, c, units, o.waves, s0.stream);
+        } else {
+            e = hipMemcpyAsync(s0.desc_dev, s0.desc_host, (size_t)c * IQA_BATCH_DESC_BYTES,
+                               hipMemcpyHostToDevice, s0.stream);
+            st = e == hipSuccess ? iqa_tiles_batched(s0.desc_dev, c, units, o.waves, s0.stream)
+                                 : IQA_OK;
+        }
+        if (st == IQA_ERR_HIP) {
+            e = (hipError_t)iqa_last_hip_error();
+            if (e == hipSuccess) e = hipErrorUnknown;
+        } else if (st != IQA_OK) {
+            break;   // a launch the scheduler would refuse the same way
+        }
+    }
+    for (Slot &s : slots)
+        if (e == hipSuccess) e = launch_publish(s);
+    for (Slot &s : slots) {
+        const hipError_t w = hipStreamSynchronize(s.stream);
+        if (e == hipSuccess) e = w;
+    }
+    const hipError_t f = hipFree(buf);
+    return e == hipSuccess ? f : e;
+}
+
 }  // namespace
 
 struct iqa_server {
@@ -415,6 +473,7 @@ iqa_status iqa_server_create(const iqa_server_opts *opts, iqa_server **out) {
             s.arena_bytes = opts->host_arena_bytes;
         }
     }
+    if (e == hipSuccess) e = warm_up(sv->slots, sv->opts);
     if (e != hipSuccess) {
         iqa_server_destroy(sv);
         return IQA_ERR_HIP;

@@ -65,6 +65,29 @@ def test_alone_equals_mix_equals_single_launch(world):
         assert same(single.lisi, req.lisi) and same(single.auglisi, req.auglisi)
 
 
+@pytest.mark.parametrize("max_batch", [1, 3, 16, 17])
+def test_servers_of_every_batch_limit_warm_up_and_serve(world, max_batch):
+    """Creation runs every launch form the batch limit allows once, on a zero
+    pair (1, 4 and 16 inline descriptors, a descriptor table); the server then
+    serves as usual, every result bitwise the single launch."""
+    specs, refs, snaps = world
+    srv, ids = make_server(refs, max_batch=max_batch)
+    plan = [(r % 4, (r // 4) % 2) for r in range(20)]
+    reqs = [srv.request(snaps[r][k][1], ids[r], 32) for r, k in plan]
+    srv.submit(reqs)
+    srv.drain()
+    comps = srv.poll(100)
+    st = srv.stats()
+    srv.close()
+    assert len(comps) == 20 and all(c["status"] == 0 for c in comps)
+    assert st["max_batch"] <= max_batch
+    for (r, k), req in zip(plan, reqs):
+        N = refs[r][1].shape[0]
+        single = iqa_tiles(snaps[r][k][1], refs[r][1], 32, cfg=serve_cfg(N, 32))
+        torch.cuda.synchronize()
+        assert same(single.lisi, req.lisi) and same(single.auglisi, req.auglisi)
+
+
 def test_results_match_oracle(world):
     specs, refs, snaps = world
     srv, ids = make_server(refs)
