@@ -130,24 +130,45 @@ __device__ __forceinline__ float dpp(float v) {
 // partner comes from a DPP permutation: quad swaps for strides 1 and 2, then
 // half-row and row mirrors for 4 and 8 (once the smaller strides have made
 // each half uniform, a mirror pairs every lane with the other half).  Across
-// rows, gfx950's permlane swaps exchange whole rows (16) or half-waves (32):
-// with both operands equal, the two results are the two halves, and their sum
-// is the same on every lane.
+// rows, gfx950's permlane swaps exchange whole rows (16) or half-waves (32).
 template <int CTRL>
 __device__ __forceinline__ void dpp_add(float &v) {
     v += dpp<CTRL>(v);
 }
 
-__device__ __forceinline__ void swap16_add(float &v) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v),
-                                                    false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+template <int W>
+__device__ __forceinline__ void permlane_swap(float &a, float &b) {
+    const auto r = W == 16 ? __builtin_amdgcn_permlane16_swap(__float_as_uint(a),
+                                                              __float_as_uint(b), false, false)
+                           : __builtin_amdgcn_permlane32_swap(__float_as_uint(a),
+                                                              __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ void swap32_add(float &v) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v),
-                                                    false, false);
-    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+// One swap level for a single value: with both operands equal, the two
+// results are the two halves of a row pair (W = 16) or of the wave (W = 32),
+// and their sum is the same on every lane.
+template <int W>
+__device__ __forceinline__ void swap_add(float &v) {
+    float a = v, b = v;
+    permlane_swap<W>(a, b);
+    v = a + b;
+}
+
+// The same level for two values with two swaps instead of two pairs of
+// swaps and adds.  Swapping between a and b leaves in one half of each row
+// pair (or wave) a's two halves and in the other b's; one add then forms a's
+// total in the first and b's in the second, with the operands in the order
+// swap_add uses, so the bits are the same.  Swapping that sum with itself
+// hands both totals to every lane.
+template <int W>
+__device__ __forceinline__ void swap_add2(float &a, float &b) {
+    permlane_swap<W>(a, b);
+    float t = a + b, u = t;
+    permlane_swap<W>(t, u);
+    a = t;
+    b = u;
 }
 
 // Plain sums over aligned groups of 2^log_g lanes; every lane of a group ends
@@ -164,14 +185,38 @@ __device__ __forceinline__ void each(Sum4 &s, Step step) {
     step(s.Y);
 }
 
+template <int MODE, int W>
+__device__ __forceinline__ void swap_level(Sum4 &s) {
+    if constexpr (MODE == kBoth) {
+        swap_add2<W>(s.A, s.P);
+    } else if constexpr (MODE == kLisi) {
+        swap_add<W>(s.A);
+    } else {
+        swap_add<W>(s.P);
+    }
+    swap_add2<W>(s.X, s.Y);
+}
+
+// log_g is uniform, so the level tests are scalar branches; marked likely,
+// they keep the levels a group needs in one straight run of code.
 template <int MODE>
 __device__ __forceinline__ Sum4 group_allreduce(Sum4 s, int log_g) {
-    if (log_g > 0) each<MODE>(s, [](float &v) { dpp_add<0xB1>(v); });   // quad_perm [1,0,3,2]
-    if (log_g > 1) each<MODE>(s, [](float &v) { dpp_add<0x4E>(v); });   // quad_perm [2,3,0,1]
-    if (log_g > 2) each<MODE>(s, [](float &v) { dpp_add<0x141>(v); });  // row_half_mirror
-    if (log_g > 3) each<MODE>(s, [](float &v) { dpp_add<0x140>(v); });  // row_mirror
-    if (log_g > 4) each<MODE>(s, [](float &v) { swap16_add(v); });
-    if (log_g > 5) each<MODE>(s, [](float &v) { swap32_add(v); });
+    if (__builtin_expect(log_g > 0, 1)) {
+        each<MODE>(s, [](float &v) { dpp_add<0xB1>(v); });    // quad_perm [1,0,3,2]
+        if (__builtin_expect(log_g > 1, 1)) {
+            each<MODE>(s, [](float &v) { dpp_add<0x4E>(v); });    // quad_perm [2,3,0,1]
+            if (__builtin_expect(log_g > 2, 1)) {
+                each<MODE>(s, [](float &v) { dpp_add<0x141>(v); });   // row_half_mirror
+                if (__builtin_expect(log_g > 3, 1)) {
+                    each<MODE>(s, [](float &v) { dpp_add<0x140>(v); });   // row_mirror
+                    if (__builtin_expect(log_g > 4, 1)) {
+                        swap_level<MODE, 16>(s);
+                        if (__builtin_expect(log_g > 5, 1)) swap_level<MODE, 32>(s);
+                    }
+                }
+            }
+        }
+    }
     return s;
 }
 
@@ -265,53 +310,44 @@ __device__ __forceinline__ void add_block(Acc &acc, const Sum4 &b) {
 // Finalisation (Eq. 1, Eq. 2)
 // ---------------------------------------------------------------------------
 
-template <int MODE>
-__device__ __forceinline__ void finalize(const KArgs &a, int64_t t, const Acc &acc) {
-    const float X1 = acc.X.hi + acc.X.lo;
-    const float Y1 = acc.Y.hi + acc.Y.lo;
-    if constexpr ((MODE & kLisi) != 0) {
-        if (a.lisi) {
-            const float A1 = acc.A.hi + acc.A.lo;
-            const float den = fmaxf(X1, Y1) + a.C2;
-            a.lisi[t] = div_pos(a.D * A1, den, __builtin_amdgcn_rcpf(den));
-        }
-    }
-    if constexpr ((MODE & kAug) != 0) {
-        if (a.aug) {
-            // S = Sx + Sy + C and q = P / S in double-float, then 1 - q.
-            float s1, e1;
-            two_sum(acc.X.hi, acc.Y.hi, s1, e1);
-            const float lo1 = e1 + (acc.X.lo + acc.Y.lo);
-            float s2, e2;
-            two_sum(s1, a.C, s2, e2);
-            float Sh, Sl;
-            two_sum(s2, lo1 + e2, Sh, Sl);
-            float Ph, Pl;
-            two_sum(acc.P.hi, acc.P.lo, Ph, Pl);
-            const float rS = __builtin_amdgcn_rcpf(Sh);
-            const float q1 = div_pos(Ph, Sh, rS);
-            float r = __builtin_fmaf(-q1, Sh, Ph);     // remainder of Ph / Sh
-            r = __builtin_fmaf(-q1, Sl, r + Pl);
-            const float q2 = r * rS;                   // correction term: a few bits suffice
-            float h, e;
-            two_sum(1.0f, -q1, h, e);
-            a.aug[t] = h + (e - q2);
-        }
-    }
-    if constexpr (MODE == kBoth) {
-        if (a.sums) {
-            float4 v;
-            v.x = acc.A.hi + acc.A.lo;
-            v.y = acc.P.hi + acc.P.lo;
-            v.z = X1;
-            v.w = Y1;
-            reinterpret_cast<float4 *>(a.sums)[t] = v;
-        }
-    }
+// A tile's sums reach these as plain FP32 values: each lane folded its
+// compensation in before the cross-lane adds.
+
+// Eq. 1.
+__device__ __forceinline__ void finalize_lisi(const KArgs &a, int64_t t, const Sum4 &s) {
+    if (!a.lisi) return;
+    const float den = fmaxf(s.X, s.Y) + a.C2;
+    a.lisi[t] = div_pos(a.D * s.A, den, __builtin_amdgcn_rcpf(den));
 }
 
-__device__ __forceinline__ Acc acc_of(const Sum4 &s) {
-    return Acc{{s.A, 0.f}, {s.P, 0.f}, {s.X, 0.f}, {s.Y, 0.f}};
+// Eq. 2: S = Sx + Sy + C and q = P / S in double-float, then 1 - q.
+__device__ __forceinline__ void finalize_aug(const KArgs &a, int64_t t, const Sum4 &s) {
+    if (!a.aug) return;
+    float s1, e1;
+    two_sum(s.X, s.Y, s1, e1);
+    float s2, e2;
+    two_sum(s1, a.C, s2, e2);
+    float Sh, Sl;
+    two_sum(s2, e1 + e2, Sh, Sl);
+    const float rS = __builtin_amdgcn_rcpf(Sh);
+    const float q1 = div_pos(s.P, Sh, rS);
+    float r = __builtin_fmaf(-q1, Sh, s.P);    // remainder of P / Sh
+    r = __builtin_fmaf(-q1, Sl, r);
+    const float q2 = r * rS;                   // correction term: a few bits suffice
+    float h, e;
+    two_sum(1.0f, -q1, h, e);
+    a.aug[t] = h + (e - q2);
+}
+
+__device__ __forceinline__ void store_sums(const KArgs &a, int64_t t, const Sum4 &s) {
+    if (a.sums) reinterpret_cast<float4 *>(a.sums)[t] = float4{s.A, s.P, s.X, s.Y};
+}
+
+template <int MODE>
+__device__ __forceinline__ void finalize(const KArgs &a, int64_t t, const Sum4 &s) {
+    if constexpr ((MODE & kLisi) != 0) finalize_lisi(a, t, s);
+    if constexpr ((MODE & kAug) != 0) finalize_aug(a, t, s);
+    if constexpr (MODE == kBoth) store_sums(a, t, s);
 }
 
 // The dispatcher hands workgroup b to XCD b % 8, and each XCD has its own L2
@@ -599,7 +635,7 @@ __device__ __forceinline__ void combine_parts(const KArgs &a, int grp, int lane)
         }
     }
     const Sum4 s = group_allreduce<MODE>(fold(c), a.log_grp);
-    if (q == 0 && tx < a.ns) finalize<MODE>(a, (int64_t)ty * a.ns + tx, acc_of(s));
+    if (q == 0 && tx < a.ns) finalize<MODE>(a, (int64_t)ty * a.ns + tx, s);
 }
 
 // A part's end of a split tile group; returns whether this workgroup
@@ -638,9 +674,13 @@ __device__ __forceinline__ bool split_finish(const KArgs &a, int grp, int part, 
 // SPLIT kernels (ks > 1 workgroups per tile group) finish through
 // split_finish; the others finalise directly, and carry no split code.
 //
+// With several waves and both indices wanted, a workgroup that is not split
+// finishes its tiles on two waves at once: wave 0 Eq. 1 (and the sums), wave
+// 1 Eq. 2, each from the same LDS tree.
+//
 // TL (diagnostic launches only) records, per workgroup, wall-clock stamps of
 // wave 0: entry, its first batch of rows reduced (first loads back), its last
-// rows reduced (last loads back), and its exit after the results are stored,
+// rows reduced (last loads back), and its exit after its results are stored,
 // plus the XCD and hardware slot it ran on: 8 uint64 per workgroup at
 // tl[8 * blockIdx.x], written with ordinary vector stores; the split part's
 // word has bit 32 set when this workgroup finished its tiles.
@@ -657,6 +697,7 @@ __device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
     const int txg = grp - ty * a.ngx;
 
     const Sum4 s = slice_sums<VEC, U, MODE, WIDE, TL>(a, ty, txg, part * WAVES + wave, lane, ts + 1);
+    constexpr bool kTwoWaveFinish = WAVES > 1 && MODE == kBoth && !SPLIT;
 
     // The tile this lane finishes, if any: a lane group's leader with one wave
     // per workgroup; lane j of wave 0 after the LDS combine otherwise.
@@ -671,7 +712,7 @@ __device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
         __shared__ float4 lds[WAVES][kWave];
         if ((lane & ((1 << a.log_grp) - 1)) == 0) lds[wave][lane >> a.log_grp] = v;
         __syncthreads();
-        if (wave != 0) return;
+        if (wave != 0 && !(kTwoWaveFinish && wave == 1)) return;
         jt = lane;
         mine = lane < a.ht && txg * a.ht + lane < a.ns;
         if (mine) {
@@ -683,8 +724,17 @@ __device__ __forceinline__ void tiles_body(const KArgs &a, uint64_t *tl) {
     }
     bool last = true;   // this workgroup finished its tiles
     if constexpr (!SPLIT) {
-        if (mine) finalize<MODE>(a, (int64_t)ty * a.ns + txg * a.ht + jt,
-                                 acc_of(Sum4{v.x, v.y, v.z, v.w}));
+        const int64_t t = (int64_t)ty * a.ns + txg * a.ht + jt;
+        const Sum4 r{v.x, v.y, v.z, v.w};
+        if constexpr (kTwoWaveFinish) {
+            if (mine && wave == 0) {
+                finalize_lisi(a, t, r);
+                store_sums(a, t, r);
+            }
+            if (mine && wave == 1) finalize_aug(a, t, r);
+        } else {
+            if (mine) finalize<MODE>(a, t, r);
+        }
     } else {
         last = split_finish<MODE>(a, grp, part, lane, mine, jt, v);
     }
@@ -785,7 +835,7 @@ __device__ __forceinline__ void batch_body(const BatchDesc *descs, int count, in
             const Sum4 s = a.cpl > 1 ? slice_sums<4, U, kBoth, true>(a, ty, txg, 0, lane)
                                      : slice_sums<4, U, kBoth, false>(a, ty, txg, 0, lane);
             const int tx = txg * a.ht + (lane >> a.log_grp);
-            if (leader && tx < a.ns) finalize<kBoth>(a, (int64_t)ty * a.ns + tx, acc_of(s));
+            if (leader && tx < a.ns) finalize<kBoth>(a, (int64_t)ty * a.ns + tx, s);
         } else {
             // Workgroup-uniform branch: every wave reaches both barriers.
             const int grp = (int)g64;
@@ -795,14 +845,22 @@ __device__ __forceinline__ void batch_body(const BatchDesc *descs, int count, in
                                      : slice_sums<4, U, kBoth, false>(a, ty, txg, wave, lane);
             if (leader) lds[wave][lane >> a.log_grp] = float4{s.A, s.P, s.X, s.Y};
             __syncthreads();
-            if (wave == 0 && lane < a.ht) {
+            // Two waves finish the tiles at once, as in the tile kernel.
+            if (wave < 2 && lane < a.ht) {
                 const int txl = txg * a.ht + lane;
                 if (txl < a.ns) {
                     float4 v[kBatchWaves];
 #pragma unroll
                     for (int w = 0; w < kBatchWaves; ++w) v[w] = lds[w][lane];
-                    const float4 t = wave_tree<kBatchWaves>(v);
-                    finalize<kBoth>(a, (int64_t)ty * a.ns + txl, acc_of(Sum4{t.x, t.y, t.z, t.w}));
+                    const float4 t4 = wave_tree<kBatchWaves>(v);
+                    const Sum4 r{t4.x, t4.y, t4.z, t4.w};
+                    const int64_t t = (int64_t)ty * a.ns + txl;
+                    if (wave == 0) {
+                        finalize_lisi(a, t, r);
+                        store_sums(a, t, r);
+                    } else {
+                        finalize_aug(a, t, r);
+                    }
                 }
             }
             __syncthreads();   // the LDS slots are reused by the next unit
@@ -886,7 +944,7 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeArgs m) {
     k.lisi = m.lisi;
     k.aug = m.aug;
     k.sums = m.sums;
-    finalize<kBoth>(k, p, acc_of(t));
+    finalize<kBoth>(k, p, t);
 }
 
 // ---------------------------------------------------------------------------
