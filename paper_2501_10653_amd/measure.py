@@ -117,6 +117,11 @@ def distinct_buffers(torch, dev, nbytes: int, pool_bytes: float) -> list:
 
 READ_MODES = {0: "regs (args preloaded)", 1: "regs (args loaded)", 2: "direct-to-LDS"}
 
+# (mode, workgroups, threads, loads in flight per lane): the shapes that came
+# out fastest for a 32 MiB launch in the full sweep, for a short run.
+QUICK_READS = [(0, 256, 512, 4), (1, 256, 512, 4), (0, 512, 256, 4), (0, 512, 512, 4),
+               (0, 1024, 256, 8), (0, 2048, 256, 4), (2, 512, 512, 8)]
+
 
 def read_floor(torch, dev, nbytes: int, K: int = 200, pool_bytes: float = 1.0 * 2 ** 30,
                plan: Optional[Plan] = None, quick: bool = False) -> Dict:
@@ -139,33 +144,34 @@ def read_floor(torch, dev, nbytes: int, K: int = 200, pool_bytes: float = 1.0 * 
             plan.add(f"empty b{blocks} t{threads} (warm)", "probe_empty", K)
             plan.add(f"empty b{blocks} t{threads}", "probe_empty", K)
 
-    blocks_set = (256, 512, 1024, 2048, 4096) if not quick else (512, 1024)
-    threads_set = (256, 512, 1024) if not quick else (256,)
-    loads_set = (4, 8, 16, 32) if not quick else (8,)
-    modes = (0, 1, 2) if not quick else (0, 2)
+    if quick:
+        shapes = QUICK_READS
+    else:
+        shapes = [(mode, blocks, threads, loads) for mode in (0, 1, 2)
+                  for blocks in (256, 512, 1024, 2048, 4096) for threads in (256, 512, 1024)
+                  for loads in (4, 8, 16, 32)]
     kname = {0: "probe_read_regs<", 1: "probe_read_regs_struct<", 2: "probe_read_lds<"}
-    for mode in modes:
-        for blocks in blocks_set:
+    said = None
+    for mode, blocks, threads, loads in shapes:
+        if (mode, blocks) != said:
             print(f"[read floor] {READ_MODES[mode]}, {blocks} workgroups", file=sys.stderr,
                   flush=True)
-            for threads in threads_set:
-                for loads in loads_set:
-                    per = math.ceil(n4 / blocks)
-                    if per < loads * threads:
-                        continue          # the loads in flight would not all be issued
-                    if mode == 2 and loads * threads * 16 > 64 * 1024:
-                        continue
-                    outs = torch.empty(blocks, device=dev)
-                    us = timer.per_launch_us(
-                        lambda i: probe_read(bufs[i % pool], outs, threads, loads, mode,
-                                             stream=stream), K)
-                    rows.append({"kind": "read", "mode": READ_MODES[mode], "blocks": blocks,
-                                 "threads": threads, "loads": loads, "us": round(us, 3),
-                                 "GBs": round(nbytes / us / 1e3, 1)})
-                    if plan:
-                        lab = f"read {READ_MODES[mode]} b{blocks} t{threads} l{loads}"
-                        plan.add(lab + " (warm)", kname[mode], K, bytes=nbytes)
-                        plan.add(lab, kname[mode], K, bytes=nbytes)
+            said = (mode, blocks)
+        per = math.ceil(n4 / blocks)
+        if per < loads * threads:
+            continue          # the loads in flight would not all be issued
+        if mode == 2 and loads * threads * 16 > 64 * 1024:
+            continue
+        outs = torch.empty(blocks, device=dev)
+        us = timer.per_launch_us(
+            lambda i: probe_read(bufs[i % pool], outs, threads, loads, mode, stream=stream), K)
+        rows.append({"kind": "read", "mode": READ_MODES[mode], "blocks": blocks,
+                     "threads": threads, "loads": loads, "us": round(us, 3),
+                     "GBs": round(nbytes / us / 1e3, 1)})
+        if plan:
+            lab = f"read {READ_MODES[mode]} b{blocks} t{threads} l{loads}"
+            plan.add(lab + " (warm)", kname[mode], K, bytes=nbytes)
+            plan.add(lab, kname[mode], K, bytes=nbytes)
     reads = [r for r in rows if r["kind"] == "read"]
     best = min(reads, key=lambda r: r["us"])
     empty = min((r for r in rows if r["kind"] == "empty"), key=lambda r: r["us"])
