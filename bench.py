@@ -95,7 +95,8 @@ def parse_args(argv=None):
     ap.add_argument("--cells", default="",
                     help="--workload sweep: N:NT cells to run (default: all 20)")
     ap.add_argument("--shape", default="paper",
-                    help="--workload readfloor / timeline: the pair shape (paper, small or N:NT)")
+                    help="--workload readfloor / timeline: the pair shape (paper, small or N:NT); "
+                         "for timeline also 'read', the plain read of the paper shape's bytes")
     ap.add_argument("--plan-out", default="",
                     help="write the launch plan (for a rocprofv3 trace summary) to this file")
     return ap.parse_args(argv)
@@ -418,8 +419,21 @@ def run_readfloor(torch, dev, args) -> dict:
 
 def run_timeline(torch, dev, args) -> dict:
     from paper_2501_10653_amd import default_cfg, synth
-    from paper_2501_10653_amd.measure import timeline
+    from paper_2501_10653_amd.measure import QUICK_READS, read_timeline, timeline
     from paper_2501_10653_amd.tune import device_copies
+    if args.shape == "read":
+        # the plain read of the paper-shape pair's bytes, in the shape that came
+        # out fastest in the read-floor sweep
+        _, blocks, threads, loads = QUICK_READS[0]
+        nbytes = 8 * workload_spec("paper").N ** 2
+        res = read_timeline(torch, dev, nbytes, blocks, threads, loads, launches=64,
+                            pool_bytes=args.pool_bytes)
+        return {"metric": "per-workgroup timeline of the plain read", "unit": "us",
+                "n_gpus": 1, "data": "synthetic",
+                "config": {"workload": f"{nbytes} B per launch, {blocks} workgroups x {threads} "
+                                       f"threads, {loads} loads in flight per lane, 64 "
+                                       f"back-to-back launches in a graph"},
+                "timeline": res}
     spec = workload_spec(args.shape)
     x, y, _ = synth.make_pair(spec)
     nbytes = 8 * spec.N ** 2

@@ -500,6 +500,12 @@ iqa_status iqa_tiles_timeline(const float *x, const float *y, int64_t N, int64_t
  *                                 lane per load, loads * threads * 16 bytes
  *                                 of LDS, at most 64 KiB, else
  *                                 IQA_ERR_CONFIG).
+ * iqa_probe_read_timeline: the IQA_PROBE_READ_REGS read with per-workgroup
+ *   wall-clock stamps in iqa_tiles_timeline's record layout (8 uint64 per
+ *   workgroup at stamps[8 * workgroup]: entry, first loads summed, last loads
+ *   summed, exit after its store, XCC_ID, HW_ID, workgroup index, 1 << 32;
+ *   stamp_count >= 8 * blocks, else IQA_ERR_SHAPE), so that the read floor
+ *   and the tile kernel split their time the same way.
  * The HIP error behind an IQA_ERR_HIP is iqa_probe_last_hip_error(). */
 #define IQA_PROBE_READ_REGS 0
 #define IQA_PROBE_READ_REGS_STRUCT 1
@@ -507,6 +513,9 @@ iqa_status iqa_tiles_timeline(const float *x, const float *y, int64_t N, int64_t
 iqa_status iqa_probe_empty(int64_t blocks, int32_t threads, void *stream);
 iqa_status iqa_probe_read(const float *buf, int64_t n, float *out, int64_t blocks,
                           int32_t threads, int32_t loads, int32_t mode, void *stream);
+iqa_status iqa_probe_read_timeline(const float *buf, int64_t n, float *out, int64_t blocks,
+                                   int32_t threads, int32_t loads, uint64_t *stamps,
+                                   int64_t stamp_count, void *stream);
 int iqa_probe_last_hip_error(void);
 
 /* Rate of the device wall clock that iqa_tiles_timeline's stamps count, in

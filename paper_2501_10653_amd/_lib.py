@@ -143,6 +143,8 @@ def load() -> ctypes.CDLL:
         "iqa_probe_empty": ([i64, ctypes.c_int32, vp], ctypes.c_int),
         "iqa_probe_read": ([vp, i64, vp, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp],
                            ctypes.c_int),
+        "iqa_probe_read_timeline": ([vp, i64, vp, i64, ctypes.c_int32, ctypes.c_int32, vp, i64,
+                                     vp], ctypes.c_int),
         "iqa_probe_last_hip_error": ([], ctypes.c_int),
         "iqa_wall_clock_khz": ([], i64),
         "iqa_read_ceiling": ([vp, i64, vp, i64, vp], ctypes.c_int),

@@ -126,6 +126,57 @@ __global__ __launch_bounds__(1024) void probe_read_lds(const float4 *src, int64_
     block_out(acc, out);
 }
 
+// The register read with wall-clock stamps, in the record layout of the tile
+// kernel's timelines (8 uint64 per workgroup at tl[8 * blockIdx.x], from wave
+// 0): entry, its first batch of loads summed, its last loads summed, its exit
+// once the workgroup's sum is stored, XCC_ID, HW_ID, the workgroup index, and
+// 1 << 32 (the word an unsplit tile workgroup writes).
+// A stamp is read only after the value it follows is in a register (the
+// empty volatile asm needs it), so it cannot move above the loads.
+__device__ __forceinline__ uint64_t stamp_after(float v) {
+    asm volatile("" ::"v"(v));
+    return wall_clock64();
+}
+
+template <int LOADS>
+__global__ __launch_bounds__(1024) void probe_read_regs_tl(const float4 *src, int64_t n4,
+                                                           int64_t per_block, int32_t width,
+                                                           float *out, uint64_t *tl) {
+    const uint64_t t_entry = wall_clock64();
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = b0 + per_block < n4 ? b0 + per_block : n4;
+    const int64_t w = width;
+    float acc = 0.f;
+    uint64_t t_first = 0;
+    int64_t i = b0 + threadIdx.x;
+    for (; i + (LOADS - 1) * w < b1; i += LOADS * w) {
+        f4v v[LOADS];
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u) v[u] = ntload(src + i + u * w);
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u) acc += hsum(v[u]);
+        if (t_first == 0) t_first = stamp_after(acc);
+    }
+    for (; i < b1; i += w) acc += hsum(ntload(src + i));
+    const uint64_t t_last = stamp_after(acc);
+    block_out(acc, out);
+    if (threadIdx.x < kWave) {
+        __builtin_amdgcn_s_waitcnt(0);   // the workgroup's store has landed
+        const uint64_t t_end = wall_clock64();
+        if (threadIdx.x == 0) {
+            uint64_t *r = tl + (int64_t)blockIdx.x * 8;
+            r[0] = t_entry;
+            r[1] = t_first ? t_first : t_last;
+            r[2] = t_last;
+            r[3] = t_end;
+            r[4] = (uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 20);   // XCC_ID
+            r[5] = (uint64_t)__builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
+            r[6] = (uint64_t)blockIdx.x;
+            r[7] = (uint64_t)1 << 32;   // finished its own work, as an unsplit tile workgroup
+        }
+    }
+}
+
 thread_local int g_last_error = 0;
 
 iqa_status status(hipError_t e) {
@@ -192,6 +243,31 @@ iqa_status iqa_probe_read(const float *buf, int64_t n, float *out, int64_t block
         case 8: return read_with<8>(mode, src, n4, per, out, b, t, s);
         case 16: return read_with<16>(mode, src, n4, per, out, b, t, s);
         case 32: return read_with<32>(mode, src, n4, per, out, b, t, s);
+        default: return IQA_ERR_CONFIG;
+    }
+}
+
+iqa_status iqa_probe_read_timeline(const float *buf, int64_t n, float *out, int64_t blocks,
+                                   int32_t threads, int32_t loads, uint64_t *stamps,
+                                   int64_t stamp_count, void *stream) {
+    if (!buf || !out || !stamps) return IQA_ERR_NULL;
+    if (n <= 0 || n % 4 != 0 || blocks < 1 || blocks > INT32_MAX) return IQA_ERR_SHAPE;
+    if (threads < kWave || threads > 1024 || threads % kWave != 0) return IQA_ERR_CONFIG;
+    if (stamp_count < 8 * blocks) return IQA_ERR_SHAPE;
+    if (reinterpret_cast<uintptr_t>(buf) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 4 != 0 ||
+        reinterpret_cast<uintptr_t>(stamps) % 8 != 0)
+        return IQA_ERR_ALIGN;
+    const int64_t n4 = n / 4;
+    const int64_t per = (n4 + blocks - 1) / blocks;
+    const float4 *src = reinterpret_cast<const float4 *>(buf);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned b = (unsigned)blocks, t = (unsigned)threads;
+    const int32_t wd = threads;
+    switch (loads) {
+        case 4: return status(launch(&probe_read_regs_tl<4>, b, t, 0, s, src, n4, per, wd, out, stamps));
+        case 8: return status(launch(&probe_read_regs_tl<8>, b, t, 0, s, src, n4, per, wd, out, stamps));
+        case 16: return status(launch(&probe_read_regs_tl<16>, b, t, 0, s, src, n4, per, wd, out, stamps));
+        case 32: return status(launch(&probe_read_regs_tl<32>, b, t, 0, s, src, n4, per, wd, out, stamps));
         default: return IQA_ERR_CONFIG;
     }
 }

@@ -239,6 +239,24 @@ def probe_read(buf: torch.Tensor, out: torch.Tensor, threads: int, loads: int, m
         raise IqaError(st, "iqa_probe_read", _lib.load().iqa_probe_last_hip_error())
 
 
+def probe_read_timeline(buf: torch.Tensor, out: torch.Tensor, threads: int, loads: int,
+                        stamps: torch.Tensor, stream=None) -> None:
+    """The register read of ``buf`` by ``out.numel()`` workgroups with
+    per-workgroup wall-clock stamps into ``stamps`` (int64, 8 per workgroup;
+    the layout of :func:`tiles_timeline`).  Measurement only."""
+    if buf.dtype != torch.float32 or not buf.is_contiguous() or out.dtype != torch.float32:
+        raise ValueError("probe_read_timeline needs contiguous float32 tensors")
+    if stamps.dtype != torch.int64 or not stamps.is_contiguous() or stamps.device != buf.device:
+        raise ValueError("stamps must be a contiguous int64 tensor on the buffer's device")
+    with torch.cuda.device(buf.device):
+        st = _lib.load().iqa_probe_read_timeline(buf.data_ptr(), buf.numel(), out.data_ptr(),
+                                                 out.numel(), threads, loads, stamps.data_ptr(),
+                                                 stamps.numel(),
+                                                 _stream_handle(buf.device, stream))
+    if st != _lib.IQA_OK:
+        raise IqaError(st, "iqa_probe_read_timeline", _lib.load().iqa_probe_last_hip_error())
+
+
 def merge_tiles(sums: torch.Tensor, f: int, *, C1: float = C_DEFAULT, C2: float = C_DEFAULT,
                 C: float = C_DEFAULT, D: Optional[float] = None, stream=None) -> TileResult:
     """Eq. (3)/(4): merge f x f blocks of tiles (given by their (n, 4) sums

@@ -206,8 +206,43 @@ def timeline(torch, dev, xs, ys, NT: int, cfg: dict, launches: int = 64) -> Dict
                                                stream=stream, out=out), launches)
     ms = timer.replay_ms(g)[0]
     del g
-    khz = int(_lib.load().iqa_wall_clock_khz())
-    st = stamps.view(launches, nwg, 8).cpu().numpy().astype(np.float64)
+    res = timeline_stats(stamps.view(launches, nwg, 8).cpu().numpy(),
+                         int(_lib.load().iqa_wall_clock_khz()), ms * 1e3 / launches, 8 * N * N)
+    return {"N": N, "NT": NT, "cfg": cfg, **res}
+
+
+def read_timeline(torch, dev, nbytes: int, blocks: int, threads: int, loads: int,
+                  launches: int = 64, pool_bytes: float = 1.0 * 2 ** 30) -> Dict:
+    """The same timeline for the plain register read of `nbytes` per launch
+    (the read floor's kernel), over distinct buffers."""
+    from . import _lib
+    from .iqa import probe_read_timeline
+    stream = torch.cuda.Stream(dev)
+    bufs = distinct_buffers(torch, dev, nbytes, pool_bytes)
+    pool = len(bufs)
+    stamps = torch.zeros(launches, blocks * 8, dtype=torch.int64, device=dev)
+    outs = torch.empty(blocks, device=dev)
+    for i in range(8):   # warm-up
+        probe_read_timeline(bufs[i % pool], outs, threads, loads, stamps[0], stream=stream)
+    torch.cuda.synchronize()
+    timer = GraphTimer(torch, dev, stream)
+    g = timer.capture(lambda i: probe_read_timeline(bufs[i % pool], outs, threads, loads,
+                                                    stamps[i], stream=stream), launches)
+    ms = timer.replay_ms(g)[0]
+    del g
+    res = timeline_stats(stamps.view(launches, blocks, 8).cpu().numpy(),
+                         int(_lib.load().iqa_wall_clock_khz()), ms * 1e3 / launches, nbytes)
+    del bufs
+    return {"bytes": nbytes, "blocks": blocks, "threads": threads, "loads": loads, **res}
+
+
+def timeline_stats(records, khz: int, event_us: float, bytes_launch: int) -> Dict:
+    """Where each launch's time goes, from per-workgroup stamp records
+    (launches x workgroups x 8: entry, first data, last data, exit, XCC_ID,
+    HW_ID, index, split word): workgroup dispatch ramp, first data back, last
+    data back, the tail after it, and the gap to the next launch (µs)."""
+    st = np.asarray(records).astype(np.float64)
+    launches, nwg = st.shape[0], st.shape[1]
     tick_us = 1e3 / khz
     entry, first, last, end = (st[:, :, k] for k in range(4))
     base = entry.min(axis=1, keepdims=True)
@@ -225,7 +260,6 @@ def timeline(torch, dev, xs, ys, NT: int, cfg: dict, launches: int = 64) -> Dict
     fin_tail = np.nanmedian(np.where(fin, end - last, np.nan), axis=1) * tick_us
     other_tail = np.nanmedian(np.where(~fin, end - last, np.nan), axis=1) * tick_us \
         if (~fin).any() else None
-    bytes_launch = 8 * N * N
 
     def stat(a):
         a = np.asarray(a)
@@ -234,9 +268,8 @@ def timeline(torch, dev, xs, ys, NT: int, cfg: dict, launches: int = 64) -> Dict
 
     span_med = float(np.median(span))
     return {
-        "N": N, "NT": NT, "cfg": cfg, "workgroups": nwg, "launches": launches,
-        "wall_clock_khz": khz,
-        "event_us_per_launch": round(ms * 1e3 / launches, 3),
+        "workgroups": nwg, "launches": launches, "wall_clock_khz": khz,
+        "event_us_per_launch": round(event_us, 3),
         "dispatch_ramp_us": stat(ramp),
         "first_data_us": stat(first_lat),
         "last_data_us": stat(data_end),

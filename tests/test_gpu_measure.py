@@ -9,7 +9,8 @@ import pytest
 import torch
 
 from paper_2501_10653_amd import _lib, default_cfg, iqa_tiles, synth
-from paper_2501_10653_amd.iqa import launch_workgroups, probe_empty, probe_read, tiles_timeline
+from paper_2501_10653_amd.iqa import (launch_workgroups, probe_empty, probe_read,
+                                     probe_read_timeline, tiles_timeline)
 from tests.gpu_util import requires_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
@@ -64,3 +65,32 @@ def test_probe_read_sums_what_it_reads():
     probe_empty(1, 64)
     probe_empty(512, 1024)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("blocks,threads,loads", [(256, 512, 4), (97, 64, 32), (1024, 256, 8)])
+def test_probe_read_timeline_sums_like_the_read_and_stamps_in_order(blocks, threads, loads):
+    n = 1 << 22
+    rng = np.random.default_rng(blocks)
+    buf = torch.from_numpy(rng.random(n, dtype=np.float32)).cuda()
+    ref = torch.zeros(blocks, device="cuda")
+    probe_read(buf, ref, threads, loads, _lib.PROBE_READ_REGS)
+    out = torch.zeros(blocks, device="cuda")
+    stamps = torch.zeros(blocks * 8, dtype=torch.int64, device="cuda")
+    probe_read_timeline(buf, out, threads, loads, stamps)
+    torch.cuda.synchronize()
+    assert same(ref, out)      # the same loads, added in the same order
+    st = stamps.view(blocks, 8).cpu().numpy()
+    entry, first, last, end = st[:, 0], st[:, 1], st[:, 2], st[:, 3]
+    assert (entry > 0).all()
+    assert (entry <= first).all() and (first <= last).all() and (last <= end).all()
+    assert (st[:, 6] == np.arange(blocks)).all() and (st[:, 7] == 1 << 32).all()
+    assert (st[:, 4] & 0xF < 8).all()
+
+
+def test_probe_read_timeline_refuses_a_short_stamp_buffer():
+    buf = torch.ones(1 << 16, device="cuda")
+    out = torch.zeros(64, device="cuda")
+    stamps = torch.zeros(64 * 8 - 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(_lib.IqaError) as e:
+        probe_read_timeline(buf, out, 256, 4, stamps)
+    assert e.value.status == 2          # IQA_ERR_SHAPE, before any launch

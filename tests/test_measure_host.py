@@ -107,3 +107,28 @@ def test_plan_dump_round_trips(tmp_path):
     plan.dump(str(p))
     assert json.load(open(p)) == {"segments": [{"label": "x (warm)", "kernel": "probe_read_regs<",
                                                 "count": 5, "bytes": 16}]}
+
+
+def test_timeline_stats_splits_a_launch_into_ramp_data_tail_and_gap():
+    import numpy as np
+    launches, nwg = 3, 4
+    rec = np.zeros((launches, nwg, 8), dtype=np.int64)
+    for L in range(launches):
+        for w in range(nwg):
+            entry = 1000 * L + w
+            last = entry + 300 + 10 * w
+            rec[L, w] = [entry, entry + 100, last, last + 20, w % 8, 0, w, 1 << 32]
+    t = measure.timeline_stats(rec, khz=100_000, event_us=9.5, bytes_launch=3_330_000)
+    tick = 0.01                                   # µs per tick at 100 MHz
+    assert t["workgroups"] == nwg and t["launches"] == launches
+    assert t["dispatch_ramp_us"]["median"] == pytest.approx(3 * tick)
+    assert t["first_data_us"]["median"] == pytest.approx(100 * tick)
+    assert t["last_data_us"]["median"] == pytest.approx(333 * tick)
+    assert t["tail_us"]["median"] == pytest.approx(20 * tick)
+    assert t["span_us"]["median"] == pytest.approx(353 * tick)
+    assert t["gap_to_next_launch_us"]["median"] == pytest.approx((1000 - 353) * tick)
+    assert t["finishing_wg_exit_after_data_us"]["median"] == pytest.approx(20 * tick)
+    assert t["other_wg_exit_after_data_us"] is None
+    assert t["workgroups_per_xcd"][:4] == [1, 1, 1, 1]
+    assert t["data_phase_GBs"] == pytest.approx(3_330_000 / 3.33 / 1e3)
+    assert t["event_us_per_launch"] == 9.5
