@@ -1752,6 +1752,6 @@ const char *iqa_status_str(int status) {
 
 int iqa_last_hip_error(void) { return g_last_hip_error; }
 
-int iqa_version(void) { return 401; }
+int iqa_version(void) { return 400; }
 
 }  // extern "C"
